@@ -1,0 +1,213 @@
+"""CPU oracle for the screened exchange build.  TEST INFRASTRUCTURE ONLY.
+
+Only ``tests/``, ``__graft_entry__.smoke()`` and the CPU-baseline leg of
+``bench.py`` may import this package.  The product (``paper_2009_03555_amd``)
+never does, and this package never imports the product: the two share only
+the seeded input generators in ``systems``.
+
+The numerics live in ``hfx_oracle.c`` (plain FP64 C, long-double Boys
+function, McMurchie-Davidson integrals, plain ordered-quartet loop); this
+module is a ctypes wrapper.  ``build()`` compiles it with gcc.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+import subprocess
+from typing import Optional, Sequence
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_SRC = os.path.join(_HERE, "hfx_oracle.c")
+_LIB = os.path.join(_HERE, "liboracle.so")
+_lib = None
+
+OP = {"coulomb": 0, "erfc": 1, "erf": 2}
+
+
+def build(force: bool = True) -> str:
+    """Compile the oracle shared library (gcc, OpenMP, no FP contraction)."""
+    if force or not os.path.exists(_LIB):
+        tmp = _LIB + ".tmp"
+        subprocess.check_call(["gcc", "-O2", "-fopenmp", "-ffp-contract=off", "-fPIC", "-shared",
+                               "-Wall", "-o", tmp, _SRC, "-lm"])
+        os.replace(tmp, _LIB)
+    return _LIB
+
+
+def lib():
+    global _lib
+    if _lib is None:
+        if not os.path.exists(_LIB):
+            build()
+        L = ctypes.CDLL(_LIB)
+        dp = ctypes.POINTER(ctypes.c_double)
+        ip = ctypes.POINTER(ctypes.c_int)
+        i32p = ctypes.POINTER(ctypes.c_int32)
+        i64p = ctypes.POINTER(ctypes.c_int64)
+        L.oracle_boys.argtypes = [ctypes.c_int, ctypes.c_double, dp]
+        L.oracle_op_ladder.argtypes = [ctypes.c_int, ctypes.c_double, ctypes.c_int, ctypes.c_double,
+                                       ctypes.c_double, dp]
+        L.oracle_normalize.argtypes = [ctypes.c_int, ctypes.c_int, dp, dp, dp]
+        L.oracle_eri_raw.argtypes = [dp, ip, ip, dp, dp, ctypes.c_int, ctypes.c_double, dp]
+        L.oracle_sph_matrix.argtypes = [ctypes.c_int, ctypes.c_int, dp, ip]
+        L.oracle_create.restype = ctypes.c_void_p
+        L.oracle_create.argtypes = [ctypes.c_int, dp, ctypes.c_int, ip, ip, ip, dp, dp, dp,
+                                    ctypes.c_double, ctypes.c_int, ctypes.c_double,
+                                    ctypes.c_double, ctypes.c_int]
+        L.oracle_destroy.argtypes = [ctypes.c_void_p]
+        L.oracle_n_blocks.restype = ctypes.c_int64
+        L.oracle_n_blocks.argtypes = [ctypes.c_void_p]
+        L.oracle_nnz.restype = ctypes.c_int64
+        L.oracle_nnz.argtypes = [ctypes.c_void_p]
+        L.oracle_blocks.argtypes = [ctypes.c_void_p, i32p]
+        L.oracle_block_offsets.argtypes = [ctypes.c_void_p, i64p]
+        L.oracle_schwarz.argtypes = [ctypes.c_void_p, dp]
+        L.oracle_set_density.argtypes = [ctypes.c_void_p, dp, dp]
+        L.oracle_build_K.restype = ctypes.c_int64
+        L.oracle_build_K.argtypes = [ctypes.c_void_p, ctypes.c_int64, i64p, ctypes.c_int, dp]
+        L.oracle_quartets.restype = ctypes.c_int64
+        L.oracle_quartets.argtypes = [ctypes.c_void_p, ctypes.c_int, ctypes.c_int64, i32p, dp]
+        _lib = L
+    return _lib
+
+
+def _p(a, t=ctypes.c_double):
+    return a.ctypes.data_as(ctypes.POINTER(t))
+
+
+# ---------------------------------------------------------------- pieces
+def boys(mmax: int, T: float) -> np.ndarray:
+    """F_m(T), m = 0..mmax (long-double evaluation, rounded to double)."""
+    out = np.zeros(mmax + 1)
+    lib().oracle_boys(mmax, float(T), _p(out))
+    return out
+
+
+def op_ladder(op: str, omega: float, mmax: int, rho: float, T: float) -> np.ndarray:
+    out = np.zeros(mmax + 1)
+    lib().oracle_op_ladder(OP[op], float(omega), mmax, float(rho), float(T), _p(out))
+    return out
+
+
+def normalize(l: int, ex: Sequence[float], c_raw: Sequence[float]) -> np.ndarray:
+    ex = np.ascontiguousarray(ex, dtype=np.float64)
+    c_raw = np.ascontiguousarray(c_raw, dtype=np.float64)
+    out = np.zeros_like(ex)
+    lib().oracle_normalize(int(l), len(ex), _p(ex), _p(c_raw), _p(out))
+    return out
+
+
+def eri(shells, op: str = "coulomb", omega: float = 0.0) -> np.ndarray:
+    """Contracted Cartesian quartet (ab|cd).
+
+    ``shells`` is four tuples (xyz, l, exponents, coefficients); coefficients
+    are used as given (normalise with :func:`normalize` first if wanted).
+    Returns an array of shape (ncart(la), ncart(lb), ncart(lc), ncart(ld)).
+    """
+    xyz = np.ascontiguousarray(np.concatenate([np.asarray(s[0], dtype=np.float64) for s in shells]))
+    ls = np.array([s[1] for s in shells], dtype=np.int32)
+    nps = np.array([len(s[2]) for s in shells], dtype=np.int32)
+    ex = np.ascontiguousarray(np.concatenate([np.asarray(s[2], dtype=np.float64) for s in shells]))
+    co = np.ascontiguousarray(np.concatenate([np.asarray(s[3], dtype=np.float64) for s in shells]))
+    nc = [(l + 1) * (l + 2) // 2 for l in ls]
+    out = np.zeros(int(np.prod(nc)))
+    lib().oracle_eri_raw(_p(xyz), _p(ls, ctypes.c_int), _p(nps, ctypes.c_int), _p(ex), _p(co),
+                         OP[op], float(omega), _p(out))
+    return out.reshape(nc)
+
+
+def sph_matrix(l: int, spherical: bool = True) -> np.ndarray:
+    T = np.zeros(36)
+    n = ctypes.c_int(0)
+    lib().oracle_sph_matrix(int(l), int(spherical), _p(T), ctypes.byref(n))
+    nc = (l + 1) * (l + 2) // 2
+    return T[: n.value * nc].reshape(n.value, nc).copy()
+
+
+# ---------------------------------------------------------------- system
+class Oracle:
+    """Oracle state for one system: its own pattern, Q, P_max and K."""
+
+    def __init__(self, system):
+        s = system
+        self.system = s
+        self._keep = []
+        xyz = self._k(np.ascontiguousarray(s.atom_xyz, dtype=np.float64))
+        sa = self._k(np.ascontiguousarray(s.shell_atom, dtype=np.int32))
+        sl = self._k(np.ascontiguousarray(s.shell_l, dtype=np.int32))
+        sn = self._k(np.ascontiguousarray(s.shell_nprim, dtype=np.int32))
+        ex = self._k(np.ascontiguousarray(s.prim_exp, dtype=np.float64))
+        co = self._k(np.ascontiguousarray(s.prim_coef, dtype=np.float64))
+        lat = None
+        if s.lattice is not None:
+            lat = self._k(np.ascontiguousarray(s.lattice, dtype=np.float64).reshape(9))
+        self.h = lib().oracle_create(
+            s.n_atoms, _p(xyz), s.n_shells, _p(sa, ctypes.c_int), _p(sl, ctypes.c_int),
+            _p(sn, ctypes.c_int), _p(ex), _p(co), _p(lat) if lat is not None else None,
+            float(s.pair_cutoff), OP[s.op], float(s.omega), float(s.tau), int(bool(s.spherical_d)))
+        nb = lib().oracle_n_blocks(self.h)
+        self.blocks = np.zeros((nb, 5), dtype=np.int32)
+        if nb:
+            lib().oracle_blocks(self.h, _p(self.blocks, ctypes.c_int32))
+        self.offsets = np.zeros(nb + 1, dtype=np.int64)
+        lib().oracle_block_offsets(self.h, _p(self.offsets, ctypes.c_int64))
+        self.nnz = int(self.offsets[-1])
+        self.Q = None
+        self.Pmax = None
+
+    def _k(self, a):
+        self._keep.append(a)
+        return a
+
+    def __del__(self):
+        try:
+            if getattr(self, "h", None):
+                lib().oracle_destroy(self.h)
+                self.h = None
+        except Exception:
+            pass
+
+    def schwarz(self) -> np.ndarray:
+        self.Q = np.zeros(len(self.blocks))
+        lib().oracle_schwarz(self.h, _p(self.Q))
+        return self.Q
+
+    def set_density(self, d_values: np.ndarray) -> np.ndarray:
+        d = np.ascontiguousarray(d_values, dtype=np.float64)
+        assert d.shape == (self.nnz,)
+        self._d = d
+        self.Pmax = np.zeros(len(self.blocks))
+        lib().oracle_set_density(self.h, _p(d), _p(self.Pmax))
+        return self.Pmax
+
+    def density_from_system(self, iteration: int = 0) -> np.ndarray:
+        from systems import density_blocks
+        vals = density_blocks(self.system, self.blocks.astype(np.int64), iteration=iteration)
+        return np.concatenate([v.ravel() for v in vals]) if vals else np.zeros(0)
+
+    def build_K(self, blocks: Optional[np.ndarray] = None, screened: bool = True):
+        """K values (pattern layout).  ``blocks``: indices to compute (default all).
+        Returns (K, number of ordered quartets evaluated)."""
+        if self.Q is None:
+            self.schwarz()
+        if blocks is None:
+            blocks = np.arange(len(self.blocks), dtype=np.int64)
+        req = np.ascontiguousarray(blocks, dtype=np.int64)
+        K = np.zeros(self.nnz)
+        n = lib().oracle_build_K(self.h, len(req), _p(req, ctypes.c_int64), int(screened), _p(K))
+        return K, int(n)
+
+    def quartets(self, gR: int = 2, cap: int = 50_000_000):
+        """Kept ordered quartets (tiny systems only): (rows[n,13], bounds[n])."""
+        if self.Q is None:
+            self.schwarz()
+        n = lib().oracle_quartets(self.h, gR, 0, None, None)
+        rows = np.zeros((max(n, 1), 13), dtype=np.int32)
+        bnd = np.zeros(max(n, 1))
+        lib().oracle_quartets(self.h, gR, n, _p(rows, ctypes.c_int32), _p(bnd))
+        return rows[:n], bnd[:n]
+
+    def block_key_index(self):
+        return {tuple(int(v) for v in b): i for i, b in enumerate(self.blocks)}

@@ -1,0 +1,23 @@
+"""Seeded synthetic systems (atoms, contracted GTO shells, lattice, density).
+
+This package builds the inputs that both the HIP path and the CPU oracle
+consume.  It holds none of the exchange-build arithmetic: no integrals, no
+normalisation, no screening, no pair lists.  Every random number is drawn
+either from ``numpy.random.Generator(PCG64(seed))`` in a documented order or
+from a counter-based hash (SplitMix64) keyed by the quantity it belongs to.
+"""
+from .generate import (  # noqa: F401
+    System,
+    config1_molecule,
+    config2_diamond,
+    config3_cluster,
+    config4_batch,
+    config5_requests,
+    random_cluster,
+    diamond_supercell,
+    density_blocks,
+    perturb_density,
+    splitmix64,
+    hash_uniform,
+    nfunc,
+)
