@@ -1,0 +1,161 @@
+/*
+ * hfx.h - C ABI of the MI355X screened exchange-matrix builder.
+ *
+ * The library evaluates screened contracted shell-quartet electron repulsion
+ * integrals (ERIs) over Cartesian Gaussian shells (s, p, d) and contracts them
+ * with a sparse density matrix D into the sparse exchange matrix K, following
+ * the paper's Background section:
+ *
+ *   Eq. (H-HFX) without its -1/2 factor,
+ *     K^G_{mu,lambda} = sum_{nu,sigma} sum_{N,H} D^{H-N}_{nu,sigma}
+ *                        (mu^0 nu^N | lambda^G sigma^H),
+ *   mu in the home cell, N, G, H lattice translations (molecules: all 0);
+ *   kernel 1/|r-r'| (full-range ERI) or erfc(omega|r-r'|)/|r-r'| (Eq. ERI-SR);
+ *   8-fold permutational symmetry with lattice translations (the permutation
+ *   relations after Eq. ERI-SR) - each unique quartet is evaluated once;
+ *   shell pairs preselected by distance and Schwarz factors (Eq. schwarz);
+ *   quartets kept iff (Q_IJ * Q_KL) * P_scr > tau with
+ *   P_scr = max(|P^IK|max, |P^IL|max, |P^JK|max, |P^JL|max) (Eq. dmscreening);
+ *   D and K stored in one shared replicated sparse block format (the sparse
+ *   format of both matrices in the Parallelization section, Table 1), with
+ *   the sparse-to-dense index transform done twice per quartet (Algorithm 4).
+ *
+ * Conventions
+ *   - Units: bohr, bohr^-2.  Lattice rows a1, a2, a3.
+ *   - Cartesian component order within a shell: lexicographic, x before y
+ *     before z (d: xx, xy, xz, yy, yz, zz), each component normalised like
+ *     x^l.  With spherical_d != 0 the boundary basis of d shells is the five
+ *     real solid harmonics m = -2..2 (sqrt3 xy, sqrt3 yz, zz-(xx+yy)/2,
+ *     sqrt3 xz, sqrt3/2 (xx-yy)); integrals and screening are Cartesian,
+ *     D_cart = T^T D T and K = T K_cart T^T at the boundary.
+ *   - D must be symmetric: D^n_{ij} = D^{-n}_{ji} (a real density matrix).
+ *   - Pattern: block (I, J, n) couples home-cell shell I with shell J
+ *     translated by n, present iff |R_I - R_J - T_n| <= pair_cutoff (all
+ *     (I, J, 0) for a molecule without cutoff).  Blocks are sorted by
+ *     (I, J, n1, n2, n3); values row-major nfunc(I) x nfunc(J) at
+ *     hfx_block.offset.  D entries outside the pattern are taken as zero and
+ *     K outside the pattern is not formed.
+ *   - Every call returns an hfx_status; no exception crosses the ABI.  On
+ *     failure hfx_last_error() returns a thread-local message.
+ *   - A plan is not thread-safe; distinct plans are independent.  All device
+ *     work of a plan runs in order on the HIP stream given to hfx_plan.
+ */
+#ifndef HFX_H
+#define HFX_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+  HFX_OK = 0,
+  HFX_ERR_INVALID = 1,     /* bad argument or system description */
+  HFX_ERR_OOM = 2,         /* device allocation failed */
+  HFX_ERR_DEVICE = 3,      /* HIP runtime error */
+  HFX_ERR_STATE = 4,       /* call out of order, or destroyed plan */
+  HFX_ERR_UNSUPPORTED = 5  /* outside the implemented range (l > 2, ...) */
+} hfx_status;
+
+typedef enum { HFX_OP_COULOMB = 0, HFX_OP_ERFC = 1 } hfx_operator;
+typedef enum { HFX_FP64 = 0, HFX_MIXED = 1 } hfx_precision;
+
+#define HFX_MAX_L 2
+#define HFX_MAX_PRIM 8
+
+/* flags for hfx_build_K */
+#define HFX_SYNC 1u        /* synchronise the stream before returning */
+#define HFX_TIMING 2u      /* record per-phase times into info (implies SYNC) */
+
+typedef struct hfx_plan_s *hfx_plan_t;
+
+/* System description.  All pointers are host memory, read during hfx_plan
+ * only (the plan copies what it needs). */
+typedef struct {
+  int32_t n_atoms;
+  const double *atom_xyz;     /* [n_atoms * 3] */
+  int32_t n_shells;
+  const int32_t *shell_atom;  /* [n_shells], 0 <= . < n_atoms */
+  const int32_t *shell_l;     /* [n_shells], 0..HFX_MAX_L */
+  const int32_t *shell_nprim; /* [n_shells], 1..HFX_MAX_PRIM */
+  const double *prim_exp;     /* [sum nprim], > 0 */
+  const double *prim_coef;    /* [sum nprim], raw; the plan normalises */
+  const double *lattice;      /* [9] rows a1,a2,a3, or NULL for a molecule */
+  double pair_cutoff;         /* bohr; <= 0: all pairs (molecules only) */
+  int32_t op;                 /* hfx_operator */
+  double omega;               /* bohr^-1, used iff op == HFX_OP_ERFC */
+  double tau;                 /* keep a quartet iff bound > tau (>= 0) */
+  int32_t precision;          /* hfx_precision */
+  double fp32_cutoff;         /* HFX_MIXED: Q_IJ*Q_KL below this -> FP32 path */
+  int32_t spherical_d;        /* 1: five spherical d functions; 0: six Cartesian */
+} hfx_system;
+
+/* One pattern block (plan-owned array, valid until hfx_plan_destroy). */
+typedef struct {
+  int32_t I, J;
+  int32_t img[3];
+  int32_t pad;
+  int64_t offset;             /* first value in the D/K arrays */
+} hfx_block;
+
+#define HFX_N_CLASSES 21
+
+/* Optional per-build report (valid once the build's stream work is done). */
+typedef struct {
+  int64_t n_quartets;                     /* unique quartets kept by screening */
+  int64_t n_quartets_class[HFX_N_CLASSES];
+  int64_t n_prim_quartets;                /* primitive quartets evaluated */
+  int64_t n_fp32_quartets;                /* quartets taken on the FP32 path */
+  double flops;                           /* algorithmic FLOPs of the ERI phase */
+  double ms_density, ms_screen, ms_eri, ms_finalize, ms_total; /* HFX_TIMING */
+} hfx_build_info;
+
+/* Device bytes hfx_plan would allocate for this system, excluding the
+ * per-build quartet list (reported separately in *list_bytes_per_quartet).
+ * Validates like hfx_plan; allocates nothing on the device. */
+hfx_status hfx_footprint(const hfx_system *sys, size_t *device_bytes, size_t *list_bytes_per_quartet);
+
+/* Validate, normalise contractions, build the pattern, shell-pair and
+ * primitive-pair tables and the block lookup, and upload them.  stream:
+ * hipStream_t (NULL = default stream).  *out receives the plan. */
+hfx_status hfx_plan(const hfx_system *sys, void *stream, hfx_plan_t *out);
+
+/* The shared D/K pattern.  *blocks points to plan-owned memory. */
+hfx_status hfx_pattern(hfx_plan_t plan, int64_t *n_blocks, int64_t *nnz, const hfx_block **blocks);
+
+/* Schwarz factors Q_IJ = sqrt(max_{i in I, j in J} |(ij|ij)|) with the
+ * plan's operator, always FP64 (Eq. schwarz).  One value per pattern block
+ * (a pair and its transpose share it).  q_host: NULL or host array of
+ * n_blocks doubles to receive them.  *n_pairs: number of unique pairs. */
+hfx_status hfx_schwarz(hfx_plan_t plan, double *q_host, int64_t *n_pairs);
+
+/* One exchange build: d_dev, k_dev are device arrays of nnz doubles in the
+ * pattern layout (caller-owned).  K is overwritten.  Runs hfx_schwarz first
+ * if it has not run.  Asynchronous on the plan's stream unless HFX_SYNC. */
+hfx_status hfx_build_K(hfx_plan_t plan, const double *d_dev, double *k_dev, uint32_t flags,
+                       hfx_build_info *info);
+
+/* Several plans (each with its own D and K) in one fused launch sequence on
+ * the first plan's stream.  Results equal n separate hfx_build_K calls. */
+hfx_status hfx_build_K_multi(int32_t n, const hfx_plan_t *plans, const double *const *d_dev,
+                             double *const *k_dev, uint32_t flags, hfx_build_info *info);
+
+/* Host copies of the last build's screening data, for verification:
+ * what = 0: P_max per pattern block (n doubles, n = n_blocks);
+ * what = 1: quartet list as uint64 (bra pair | ket pair << 24 | image << 48),
+ *           n = number of quartets;
+ * what = 2: unique pair table as int32 [n][6] (A, B, n1, n2, n3, class);
+ * what = 3: Schwarz factor per unique pair (n doubles).
+ * With host == NULL only *n is set. */
+hfx_status hfx_export(hfx_plan_t plan, int32_t what, void *host, int64_t *n);
+
+hfx_status hfx_plan_destroy(hfx_plan_t plan);
+
+const char *hfx_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* HFX_H */

@@ -1,0 +1,226 @@
+// ERI + digest kernels and Schwarz-diagonal kernels, one instantiation per
+// angular-momentum class.  Included by eri_r<cb><ck>.hip (one translation
+// unit per class region, compiled in parallel).
+#pragma once
+#include "launchers.hpp"
+#include "os_hgp.hpp"
+
+namespace hfx {
+
+// ----------------------------------------------------------------- digest
+// The four "row-first" exchange contributions of one unique quartet
+// (A^0 B^nB | C^G D^(G+nD)) with weight w; K = K4 + K4^T is formed later.
+// Block indices: AC = (A,C,G), AD = (A,D,G+nD), BC = (B,C,G-nB),
+// BD = (B,D,G+nD-nB); absent blocks (-1) drop their terms.
+//   K[AC][a][c] += w sum_bd v D[BD][b][d]      K[BC][b][c] += w sum_ad v D[AD][a][d]
+//   K[AD][a][d] += w sum_bc v D[BC][b][c]      K[BD][b][d] += w sum_ac v D[AC][a][c]
+template <class C>
+__device__ __forceinline__ void digest(const DevSys &s, int bAC, int bAD, int bBC, int bBD, const double *v,
+                                       double w, const double *__restrict__ Dc, double *__restrict__ K4) {
+  constexpr int NA = C::NA, NB = C::NB, NC = C::NC, ND = C::ND;
+  auto V = [&](int a, int b, int c, int d) { return v[((a * NB + b) * NC + c) * ND + d]; };
+  if (bAC >= 0 && bBD >= 0) {
+    const double *D = Dc + s.blk_coff[bBD];
+    double dv[NB * ND];
+#pragma unroll
+    for (int k = 0; k < NB * ND; ++k) dv[k] = D[k];
+    double *K = K4 + s.blk_coff[bAC];
+#pragma unroll
+    for (int a = 0; a < NA; ++a)
+#pragma unroll
+      for (int c = 0; c < NC; ++c) {
+        double acc = 0.0;
+#pragma unroll
+        for (int b = 0; b < NB; ++b)
+#pragma unroll
+          for (int d = 0; d < ND; ++d) acc = fma(V(a, b, c, d), dv[b * ND + d], acc);
+        unsafeAtomicAdd(K + a * NC + c, w * acc);
+      }
+  }
+  if (bBC >= 0 && bAD >= 0) {
+    const double *D = Dc + s.blk_coff[bAD];
+    double dv[NA * ND];
+#pragma unroll
+    for (int k = 0; k < NA * ND; ++k) dv[k] = D[k];
+    double *K = K4 + s.blk_coff[bBC];
+#pragma unroll
+    for (int b = 0; b < NB; ++b)
+#pragma unroll
+      for (int c = 0; c < NC; ++c) {
+        double acc = 0.0;
+#pragma unroll
+        for (int a = 0; a < NA; ++a)
+#pragma unroll
+          for (int d = 0; d < ND; ++d) acc = fma(V(a, b, c, d), dv[a * ND + d], acc);
+        unsafeAtomicAdd(K + b * NC + c, w * acc);
+      }
+  }
+  if (bAD >= 0 && bBC >= 0) {
+    const double *D = Dc + s.blk_coff[bBC];
+    double dv[NB * NC];
+#pragma unroll
+    for (int k = 0; k < NB * NC; ++k) dv[k] = D[k];
+    double *K = K4 + s.blk_coff[bAD];
+#pragma unroll
+    for (int a = 0; a < NA; ++a)
+#pragma unroll
+      for (int d = 0; d < ND; ++d) {
+        double acc = 0.0;
+#pragma unroll
+        for (int b = 0; b < NB; ++b)
+#pragma unroll
+          for (int c = 0; c < NC; ++c) acc = fma(V(a, b, c, d), dv[b * NC + c], acc);
+        unsafeAtomicAdd(K + a * ND + d, w * acc);
+      }
+  }
+  if (bBD >= 0 && bAC >= 0) {
+    const double *D = Dc + s.blk_coff[bAC];
+    double dv[NA * NC];
+#pragma unroll
+    for (int k = 0; k < NA * NC; ++k) dv[k] = D[k];
+    double *K = K4 + s.blk_coff[bBD];
+#pragma unroll
+    for (int b = 0; b < NB; ++b)
+#pragma unroll
+      for (int d = 0; d < ND; ++d) {
+        double acc = 0.0;
+#pragma unroll
+        for (int a = 0; a < NA; ++a)
+#pragma unroll
+          for (int c = 0; c < NC; ++c) acc = fma(V(a, b, c, d), dv[a * NC + c], acc);
+        unsafeAtomicAdd(K + b * ND + d, w * acc);
+      }
+  }
+}
+
+// --------------------------------------------------------- ERI + digest
+// One lane per unique quartet of the class segment (grid-stride loop).
+template <int CB, int CK, int OP>
+__global__ __launch_bounds__(256) void eri_digest_kernel(DevSys s, const uint64_t *__restrict__ list,
+                                                         int64_t nq, const double *__restrict__ Dc,
+                                                         double *__restrict__ K4,
+                                                         unsigned long long *__restrict__ nprim) {
+  using C = Cls<class_la(CB), class_lb(CB), class_la(CK), class_lb(CK)>;
+  const int64_t nthreads = (int64_t)gridDim.x * blockDim.x;
+  unsigned long long prims = 0;
+  for (int64_t qi = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; qi < nq; qi += nthreads) {
+    const uint64_t q = list[qi];
+    const int bra = (int)(q & 0xFFFFFFull);
+    const int ket = (int)((q >> 24) & 0xFFFFFFull);
+    int g1, g2, g3;
+    unpack_img5((uint32_t)(q >> 48), g1, g2, g3);
+    const int4 bi = s.pr_info[bra], ki = s.pr_info[ket];
+    const int2 bpp = s.pr_pp[bra], kpp = s.pr_pp[ket];
+    double gx = 0.0, gy = 0.0, gz = 0.0;
+    if (s.periodic) {
+      gx = g1 * s.lat[0] + g2 * s.lat[3] + g3 * s.lat[6];
+      gy = g1 * s.lat[1] + g2 * s.lat[4] + g3 * s.lat[7];
+      gz = g1 * s.lat[2] + g2 * s.lat[5] + g3 * s.lat[8];
+    }
+    double acc[C::NACC];
+#pragma unroll
+    for (int k = 0; k < C::NACC; ++k) acc[k] = 0.0;
+    prim_sum<C, OP>(s, s.pp + (int64_t)bpp.x * kPP, bpp.y, s.pp + (int64_t)kpp.x * kPP, kpp.y, gx, gy, gz,
+                    0, 1, acc);
+    prims += (unsigned long long)bpp.y * kpp.y;
+    const double *bg = s.pr_geom + (int64_t)bra * 8;
+    const double *kg = s.pr_geom + (int64_t)ket * 8;
+    double AB[3] = {bg[0], bg[1], bg[2]};
+    double CD[3] = {kg[0], kg[1], kg[2]};
+    double out[C::NOUT];
+    hrr<C>(acc, AB, CD, out);
+    int nB1, nB2, nB3, nD1, nD2, nD3;
+    unpack_img8(bi.z, nB1, nB2, nB3);
+    unpack_img8(ki.z, nD1, nD2, nD3);
+    const int A = bi.x, B = bi.y, Cs = ki.x, Ds = ki.y;
+    const int bAC = lookup(s, A, Cs, g1, g2, g3);
+    const int bAD = lookup(s, A, Ds, g1 + nD1, g2 + nD2, g3 + nD3);
+    const int bBC = lookup(s, B, Cs, g1 - nB1, g2 - nB2, g3 - nB3);
+    const int bBD = lookup(s, B, Ds, g1 + nD1 - nB1, g2 + nD2 - nB2, g3 + nD3 - nB3);
+    double w = 1.0;
+    if (bi.w & 1) w *= 0.5;
+    if (ki.w & 1) w *= 0.5;
+    if (bra == ket && g1 == 0 && g2 == 0 && g3 == 0) w *= 0.5;
+    digest<C>(s, bAC, bAD, bBC, bBD, out, w, Dc, K4);
+  }
+  // one counter update per thread
+  prims += __shfl_xor(prims, 1);
+  prims += __shfl_xor(prims, 2);
+  prims += __shfl_xor(prims, 4);
+  prims += __shfl_xor(prims, 8);
+  prims += __shfl_xor(prims, 16);
+  prims += __shfl_xor(prims, 32);
+  if ((threadIdx.x & 63) == 0 && prims) atomicAdd(nprim, prims);
+}
+
+// ------------------------------------------------------------ Schwarz
+// Q_p = sqrt(max_{a,b} |(ab|ab)|) over all primitive pairs of pair p.
+template <int CB, int OP>
+__global__ __launch_bounds__(128) void schwarz_kernel(DevSys s, int p0, int p1) {
+  using C = Cls<class_la(CB), class_lb(CB), class_la(CB), class_lb(CB)>;
+  const int p = p0 + (int)(blockIdx.x * blockDim.x + threadIdx.x);
+  if (p >= p1) return;
+  const int2 pp = s.pr_pp[p];
+  const int n = s.pr_npp[p];
+  double acc[C::NACC];
+#pragma unroll
+  for (int k = 0; k < C::NACC; ++k) acc[k] = 0.0;
+  const double *b = s.pp + (int64_t)pp.x * kPP;
+  prim_sum<C, OP>(s, b, n, b, n, 0.0, 0.0, 0.0, 0, 1, acc);
+  const double *g = s.pr_geom + (int64_t)p * 8;
+  double AB[3] = {g[0], g[1], g[2]};
+  double out[C::NOUT];
+  hrr<C>(acc, AB, AB, out);
+  double m = 0.0;
+#pragma unroll
+  for (int a = 0; a < C::NA; ++a)
+#pragma unroll
+    for (int bb = 0; bb < C::NB; ++bb) m = fmax(m, fabs(out[((a * C::NB + bb) * C::NA + a) * C::NB + bb]));
+  s.pr_Q[p] = sqrt(m);
+}
+
+// ------------------------------------------------------------ launchers
+template <int CB, int CK, int OP>
+void launch_eri_t(const DevSys &s, const uint64_t *list, int64_t nq, const double *Dc, double *K4,
+                  unsigned long long *nprim, hipStream_t st) {
+  if (nq <= 0) return;
+  const int threads = 256;
+  int64_t blocks = (nq + threads - 1) / threads;
+  if (blocks > 256 * 64) blocks = 256 * 64;
+  hipLaunchKernelGGL((eri_digest_kernel<CB, CK, OP>), dim3((unsigned)blocks), dim3(threads), 0, st, s, list,
+                     nq, Dc, K4, nprim);
+}
+
+template <int CB, int OP>
+void launch_schwarz_t(const DevSys &s, int p0, int p1, hipStream_t st) {
+  if (p1 <= p0) return;
+  const int threads = 128;
+  hipLaunchKernelGGL((schwarz_kernel<CB, OP>), dim3((p1 - p0 + threads - 1) / threads), dim3(threads), 0, st, s,
+                     p0, p1);
+}
+
+}  // namespace hfx
+
+// Instantiate the launchers of one class region (bra class CB, ket class
+// CK <= CB) in this translation unit; the diagonal unit (CK == CB) also holds
+// the Schwarz kernels of pair class CB.
+#define HFX_ERI_UNIT(CB, CK)                                                                         \
+  namespace hfx {                                                                                    \
+  void launch_eri_r##CB##CK(int op, const DevSys &s, const uint64_t *l, int64_t n, const double *D,  \
+                            double *K, unsigned long long *c, hipStream_t st) {                      \
+    if (op == 0)                                                                                     \
+      launch_eri_t<CB, CK, 0>(s, l, n, D, K, c, st);                                                 \
+    else                                                                                             \
+      launch_eri_t<CB, CK, 1>(s, l, n, D, K, c, st);                                                 \
+  }                                                                                                  \
+  }
+
+#define HFX_SCHWARZ_UNIT(CB)                                                                         \
+  namespace hfx {                                                                                    \
+  void launch_schwarz_c##CB(int op, const DevSys &s, int p0, int p1, hipStream_t st) {              \
+    if (op == 0)                                                                                     \
+      launch_schwarz_t<CB, 0>(s, p0, p1, st);                                                        \
+    else                                                                                             \
+      launch_schwarz_t<CB, 1>(s, p0, p1, st);                                                        \
+  }                                                                                                  \
+  }

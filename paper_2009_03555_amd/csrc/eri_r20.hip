@@ -1,0 +1,3 @@
+// ERI + digest kernels of bra pair class 2, ket pair class 0.
+#include "eri_kernels.hpp"
+HFX_ERI_UNIT(2, 0)

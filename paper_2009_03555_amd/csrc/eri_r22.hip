@@ -1,0 +1,4 @@
+// ERI + digest kernels of bra pair class 2, ket pair class 2.
+#include "eri_kernels.hpp"
+HFX_ERI_UNIT(2, 2)
+HFX_SCHWARZ_UNIT(2)

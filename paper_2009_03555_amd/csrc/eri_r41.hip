@@ -1,0 +1,3 @@
+// ERI + digest kernels of bra pair class 4, ket pair class 1.
+#include "eri_kernels.hpp"
+HFX_ERI_UNIT(4, 1)

@@ -1,0 +1,4 @@
+// ERI + digest kernels of bra pair class 4, ket pair class 4.
+#include "eri_kernels.hpp"
+HFX_ERI_UNIT(4, 4)
+HFX_SCHWARZ_UNIT(4)

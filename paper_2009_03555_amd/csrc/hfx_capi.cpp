@@ -1,0 +1,871 @@
+// C ABI of the exchange builder: validation, host plan (normalisation,
+// pattern, shell-pair and primitive-pair tables, block lookup, Boys table),
+// device upload, and the build sequence (density -> screen -> ERI -> K).
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <mutex>
+#include <string>
+#include <unordered_set>
+#include <vector>
+
+#include "../../include/hfx.h"
+#include "launchers.hpp"
+
+using namespace hfx;
+
+namespace {
+
+thread_local std::string g_err;
+
+hfx_status fail(hfx_status st, const std::string &msg) {
+  g_err = msg;
+  return st;
+}
+
+#define HIPCHK(expr)                                                                                   \
+  do {                                                                                                 \
+    hipError_t e_ = (expr);                                                                            \
+    if (e_ != hipSuccess)                                                                              \
+      return fail(e_ == hipErrorOutOfMemory ? HFX_ERR_OOM : HFX_ERR_DEVICE,                            \
+                  std::string(#expr) + ": " + hipGetErrorString(e_));                                 \
+  } while (0)
+
+constexpr uint32_t kMagic = 0x48465850u;  // "HFXP"
+constexpr double kPrimDrop = 1e-20;      // primitive-pair bound below which the ERI path skips it
+
+bool lexpos(int a, int b, int c) { return a > 0 || (a == 0 && (b > 0 || (b == 0 && c >= 0))); }
+
+double dfact(int n) {
+  double r = 1.0;
+  for (int k = n; k > 1; k -= 2) r *= k;
+  return r;
+}
+
+int nfunc_host(int l, int sph) { return (l == 2 && sph) ? 5 : (l + 1) * (l + 2) / 2; }
+
+// Boys table: F_m(T_i) by the everywhere-convergent series
+// F_m(T) = e^-T sum_k (2T)^k / ((2m+1)(2m+3)...(2m+2k+1)) at the top order,
+// downward recursion below it, all in long double.
+std::vector<double> boys_table() {
+  std::vector<double> t((size_t)kBoysRows * kBoysCols);
+  const int mtop = kBoysCols - 2;  // 15
+  for (int i = 0; i < kBoysRows; ++i) {
+    long double T = (long double)i * (long double)kBoysStep;
+    long double et = expl(-T);
+    long double term = 1.0L / (2 * mtop + 1), sum = term;
+    for (int k = 1; k < 100000; ++k) {
+      term *= 2.0L * T / (2 * mtop + 2 * k + 1);
+      sum += term;
+      if (term < sum * 1e-22L) break;
+    }
+    long double F[kBoysCols];
+    F[mtop] = et * sum;
+    for (int m = mtop - 1; m >= 0; --m) F[m] = (2.0L * T * F[m + 1] + et) / (2 * m + 1);
+    for (int m = 0; m <= mtop; ++m) t[(size_t)i * kBoysCols + m] = (double)F[m];
+    t[(size_t)i * kBoysCols + kBoysCols - 1] = (double)et;
+  }
+  return t;
+}
+
+struct DevMem {
+  std::vector<void *> ptrs;
+  size_t total = 0;
+  template <typename T>
+  hipError_t alloc(T **p, size_t n) {
+    *p = nullptr;
+    if (n == 0) n = 1;
+    hipError_t e = hipMalloc((void **)p, n * sizeof(T));
+    if (e == hipSuccess) {
+      ptrs.push_back((void *)*p);
+      total += n * sizeof(T);
+    }
+    return e;
+  }
+  void release() {
+    for (void *p : ptrs) (void)hipFree(p);
+    ptrs.clear();
+    total = 0;
+  }
+};
+
+}  // namespace
+
+struct hfx_plan_s {
+  uint32_t magic = kMagic;
+  // ---- system
+  int n_atoms = 0, nsh = 0;
+  std::vector<double> atom_xyz, sh_xyz;
+  std::vector<int32_t> sh_atom, sh_l, sh_np, sh_poff;
+  std::vector<double> ex, cn;  // exponents, normalised coefficients
+  bool periodic = false;
+  double lat[9] = {0}, rec[9] = {0}, recn[3] = {0};
+  double cutoff = 0.0;
+  int op = 0;
+  double omega = 0.0, tau = 0.0;
+  int precision = 0;
+  double fp32_cutoff = 0.0;
+  int sph = 1;
+  // ---- pattern
+  std::vector<hfx_block> blocks;
+  std::vector<int2> blk_IJ;
+  std::vector<int64_t> blk_off, blk_coff;
+  std::vector<int32_t> partner, block_pair;
+  std::vector<uint8_t> canon;
+  int64_t nnz = 0, nnz_c = 0;
+  int imgR[3] = {0, 0, 0};
+  int nimg = 1;
+  std::vector<int32_t> lut;
+  // ---- unique pairs
+  std::vector<int4> pr_info;
+  std::vector<double> pr_geom;
+  std::vector<int2> pr_pp;
+  std::vector<int32_t> pr_npp;
+  std::vector<double> pp;
+  int32_t class_start[kNPairClass + 1] = {0};
+  // ---- screening items
+  std::vector<int2> items;
+  int64_t region_item[kNQuartetClass + 1] = {0};
+  // ---- device
+  hipStream_t stream = nullptr;
+  DevMem mem;
+  DevSys ds{};
+  double *d_sh_xyz = nullptr;
+  int32_t *d_sh_l = nullptr;
+  int4 *d_pr_info = nullptr;
+  double *d_pr_geom = nullptr;
+  int2 *d_pr_pp = nullptr;
+  int32_t *d_pr_npp = nullptr;
+  double *d_pr_Q = nullptr;
+  double *d_pp = nullptr;
+  int32_t *d_lut = nullptr;
+  int2 *d_blk_IJ = nullptr;
+  int64_t *d_blk_off = nullptr, *d_blk_coff = nullptr;
+  int32_t *d_partner = nullptr;
+  uint8_t *d_canon = nullptr;
+  double *d_pmax = nullptr;
+  unsigned long long *d_pglob = nullptr;
+  double *d_Dc = nullptr, *d_K4 = nullptr;
+  double *d_boys = nullptr;
+  int2 *d_items = nullptr;
+  int32_t *d_counts = nullptr;
+  int64_t *d_offsets = nullptr;
+  void *d_scan_tmp = nullptr;
+  size_t scan_tmp_bytes = 0;
+  int32_t *d_class_start = nullptr;
+  int32_t *d_err = nullptr;
+  unsigned long long *d_nprim = nullptr;  // per region
+  uint64_t *d_list = nullptr;
+  int64_t list_cap = 0;
+  bool schwarz_done = false;
+  // ---- last build
+  int64_t region_q[kNQuartetClass + 1] = {0};
+  int64_t nq_total = 0;
+};
+
+namespace {
+
+bool finite(double x) { return std::isfinite(x); }
+
+hfx_status validate(const hfx_system *s) {
+  if (!s) return fail(HFX_ERR_INVALID, "system is NULL");
+  if (s->n_atoms <= 0 || !s->atom_xyz) return fail(HFX_ERR_INVALID, "no atoms");
+  if (s->n_shells <= 0 || !s->shell_atom || !s->shell_l || !s->shell_nprim || !s->prim_exp || !s->prim_coef)
+    return fail(HFX_ERR_INVALID, "no shells or NULL shell arrays");
+  for (int i = 0; i < 3 * s->n_atoms; ++i)
+    if (!finite(s->atom_xyz[i])) return fail(HFX_ERR_INVALID, "non-finite atom coordinate");
+  int64_t np = 0;
+  for (int i = 0; i < s->n_shells; ++i) {
+    if (s->shell_atom[i] < 0 || s->shell_atom[i] >= s->n_atoms) return fail(HFX_ERR_INVALID, "shell_atom out of range");
+    if (s->shell_l[i] < 0) return fail(HFX_ERR_INVALID, "negative angular momentum");
+    if (s->shell_l[i] > HFX_MAX_L) return fail(HFX_ERR_UNSUPPORTED, "angular momentum above d is not implemented");
+    if (s->shell_nprim[i] < 1 || s->shell_nprim[i] > HFX_MAX_PRIM)
+      return fail(HFX_ERR_INVALID, "shell_nprim outside 1..HFX_MAX_PRIM");
+    np += s->shell_nprim[i];
+  }
+  for (int64_t k = 0; k < np; ++k) {
+    if (!(s->prim_exp[k] > 0.0) || !finite(s->prim_exp[k])) return fail(HFX_ERR_INVALID, "exponent must be positive and finite");
+    if (!finite(s->prim_coef[k])) return fail(HFX_ERR_INVALID, "non-finite contraction coefficient");
+  }
+  if (s->lattice) {
+    for (int i = 0; i < 9; ++i)
+      if (!finite(s->lattice[i])) return fail(HFX_ERR_INVALID, "non-finite lattice");
+    const double *a = s->lattice;
+    double det = a[0] * (a[4] * a[8] - a[5] * a[7]) - a[1] * (a[3] * a[8] - a[5] * a[6]) + a[2] * (a[3] * a[7] - a[4] * a[6]);
+    double n1 = std::sqrt(a[0] * a[0] + a[1] * a[1] + a[2] * a[2]);
+    double n2 = std::sqrt(a[3] * a[3] + a[4] * a[4] + a[5] * a[5]);
+    double n3 = std::sqrt(a[6] * a[6] + a[7] * a[7] + a[8] * a[8]);
+    if (!(std::fabs(det) > 1e-8 * n1 * n2 * n3)) return fail(HFX_ERR_INVALID, "singular lattice");
+    if (!(s->pair_cutoff > 0.0)) return fail(HFX_ERR_INVALID, "a periodic system needs pair_cutoff > 0");
+  }
+  if (!finite(s->pair_cutoff)) return fail(HFX_ERR_INVALID, "non-finite pair_cutoff");
+  if (s->op != HFX_OP_COULOMB && s->op != HFX_OP_ERFC) return fail(HFX_ERR_INVALID, "unknown operator");
+  if (s->op == HFX_OP_ERFC && !(s->omega > 0.0 && finite(s->omega))) return fail(HFX_ERR_INVALID, "erfc needs omega > 0");
+  if (!(s->tau >= 0.0) || !finite(s->tau)) return fail(HFX_ERR_INVALID, "tau must be >= 0");
+  if (s->precision != HFX_FP64 && s->precision != HFX_MIXED) return fail(HFX_ERR_INVALID, "unknown precision");
+  if (!(s->fp32_cutoff >= 0.0) || !finite(s->fp32_cutoff)) return fail(HFX_ERR_INVALID, "fp32_cutoff must be >= 0");
+  return HFX_OK;
+}
+
+// Contraction normalisation: primitive x^l normalisation
+// N = (2a/pi)^(3/4) (4a)^(l/2) / sqrt((2l-1)!!) folded into c, then c scaled
+// so that the x^l component of the contracted shell has unit self-overlap.
+void normalise(int l, int n, const double *ex, const double *c, double *out) {
+  const double pi = 3.14159265358979323846;
+  double N[HFX_MAX_PRIM];
+  for (int k = 0; k < n; ++k) N[k] = std::pow(2.0 * ex[k] / pi, 0.75) * std::pow(4.0 * ex[k], 0.5 * l) / std::sqrt(dfact(2 * l - 1));
+  double S = 0.0;
+  for (int i = 0; i < n; ++i)
+    for (int j = 0; j < n; ++j) {
+      double p = ex[i] + ex[j];
+      S += c[i] * N[i] * c[j] * N[j] * std::pow(pi / p, 1.5) * dfact(2 * l - 1) / std::pow(2.0 * p, l);
+    }
+  for (int k = 0; k < n; ++k) out[k] = c[k] * N[k] / std::sqrt(S);
+}
+
+void lattice_vec(const hfx_plan_s &P, int a, int b, int c, double *t) {
+  for (int k = 0; k < 3; ++k) t[k] = a * P.lat[k] + b * P.lat[3 + k] + c * P.lat[6 + k];
+}
+
+hfx_status build_host(hfx_plan_s &P, const hfx_system *s) {
+  P.n_atoms = s->n_atoms;
+  P.nsh = s->n_shells;
+  P.atom_xyz.assign(s->atom_xyz, s->atom_xyz + 3 * s->n_atoms);
+  P.sh_atom.assign(s->shell_atom, s->shell_atom + P.nsh);
+  P.sh_l.assign(s->shell_l, s->shell_l + P.nsh);
+  P.sh_np.assign(s->shell_nprim, s->shell_nprim + P.nsh);
+  P.sh_poff.resize(P.nsh + 1);
+  int tot = 0;
+  for (int i = 0; i < P.nsh; ++i) {
+    P.sh_poff[i] = tot;
+    tot += P.sh_np[i];
+  }
+  P.sh_poff[P.nsh] = tot;
+  P.ex.assign(s->prim_exp, s->prim_exp + tot);
+  P.cn.resize(tot);
+  for (int i = 0; i < P.nsh; ++i)
+    normalise(P.sh_l[i], P.sh_np[i], &P.ex[P.sh_poff[i]], s->prim_coef + P.sh_poff[i], &P.cn[P.sh_poff[i]]);
+  P.sh_xyz.resize(3 * P.nsh);
+  for (int i = 0; i < P.nsh; ++i)
+    for (int k = 0; k < 3; ++k) P.sh_xyz[3 * i + k] = P.atom_xyz[3 * P.sh_atom[i] + k];
+  P.periodic = s->lattice != nullptr;
+  P.cutoff = s->pair_cutoff;
+  P.op = s->op;
+  P.omega = s->omega;
+  P.tau = s->tau;
+  P.precision = s->precision;
+  P.fp32_cutoff = s->fp32_cutoff;
+  P.sph = s->spherical_d ? 1 : 0;
+
+  // ---- lattice and image search box
+  int box[3] = {0, 0, 0};
+  if (P.periodic) {
+    std::memcpy(P.lat, s->lattice, sizeof(P.lat));
+    const double *a = P.lat;
+    double det = a[0] * (a[4] * a[8] - a[5] * a[7]) - a[1] * (a[3] * a[8] - a[5] * a[6]) + a[2] * (a[3] * a[7] - a[4] * a[6]);
+    // b_i (rows) with b_i . a_j = delta_ij: b = (A^-1)^T
+    double inv[9] = {(a[4] * a[8] - a[5] * a[7]) / det, (a[2] * a[7] - a[1] * a[8]) / det, (a[1] * a[5] - a[2] * a[4]) / det,
+                     (a[5] * a[6] - a[3] * a[8]) / det, (a[0] * a[8] - a[2] * a[6]) / det, (a[2] * a[3] - a[0] * a[5]) / det,
+                     (a[3] * a[7] - a[4] * a[6]) / det, (a[1] * a[6] - a[0] * a[7]) / det, (a[0] * a[4] - a[1] * a[3]) / det};
+    for (int i = 0; i < 3; ++i) {
+      for (int k = 0; k < 3; ++k) P.rec[3 * i + k] = inv[3 * k + i];
+      P.recn[i] = std::sqrt(P.rec[3 * i] * P.rec[3 * i] + P.rec[3 * i + 1] * P.rec[3 * i + 1] + P.rec[3 * i + 2] * P.rec[3 * i + 2]);
+    }
+    for (int i = 0; i < 3; ++i) {
+      double fmin = 1e300, fmax = -1e300;
+      for (int at = 0; at < P.n_atoms; ++at) {
+        double f = P.rec[3 * i] * P.atom_xyz[3 * at] + P.rec[3 * i + 1] * P.atom_xyz[3 * at + 1] + P.rec[3 * i + 2] * P.atom_xyz[3 * at + 2];
+        fmin = std::min(fmin, f);
+        fmax = std::max(fmax, f);
+      }
+      box[i] = (int)std::ceil(P.cutoff * P.recn[i] + (fmax - fmin)) + 1;
+      if (box[i] > 100) return fail(HFX_ERR_UNSUPPORTED, "pair cutoff spans too many lattice images");
+    }
+  }
+
+  // ---- pattern: atom pairs within the cutoff, expanded to shells
+  std::vector<std::vector<int>> atom_shells(P.n_atoms);
+  for (int i = 0; i < P.nsh; ++i) atom_shells[P.sh_atom[i]].push_back(i);
+  struct Key {
+    int32_t I, J, a, b, c;
+  };
+  std::vector<Key> keys;
+  const double rc2 = P.cutoff * P.cutoff;
+  for (int ia = 0; ia < P.n_atoms; ++ia)
+    for (int ib = 0; ib < P.n_atoms; ++ib)
+      for (int a = -box[0]; a <= box[0]; ++a)
+        for (int b = -box[1]; b <= box[1]; ++b)
+          for (int c = -box[2]; c <= box[2]; ++c) {
+            double t[3] = {0, 0, 0};
+            if (P.periodic) lattice_vec(P, a, b, c, t);
+            double d2 = 0.0;
+            for (int k = 0; k < 3; ++k) {
+              double d = P.atom_xyz[3 * ia + k] - P.atom_xyz[3 * ib + k] - t[k];
+              d2 += d * d;
+            }
+            if (P.cutoff > 0.0 && d2 > rc2) continue;
+            for (int I : atom_shells[ia])
+              for (int J : atom_shells[ib]) keys.push_back({I, J, a, b, c});
+          }
+  std::sort(keys.begin(), keys.end(), [](const Key &x, const Key &y) {
+    if (x.I != y.I) return x.I < y.I;
+    if (x.J != y.J) return x.J < y.J;
+    if (x.a != y.a) return x.a < y.a;
+    if (x.b != y.b) return x.b < y.b;
+    return x.c < y.c;
+  });
+  const int64_t nb = (int64_t)keys.size();
+  if (nb >= (int64_t)INT32_MAX) return fail(HFX_ERR_UNSUPPORTED, "too many pattern blocks");
+  for (auto &k : keys) {
+    P.imgR[0] = std::max(P.imgR[0], std::abs(k.a));
+    P.imgR[1] = std::max(P.imgR[1], std::abs(k.b));
+    P.imgR[2] = std::max(P.imgR[2], std::abs(k.c));
+  }
+  P.nimg = (2 * P.imgR[0] + 1) * (2 * P.imgR[1] + 1) * (2 * P.imgR[2] + 1);
+  const int64_t lut_n = (int64_t)P.nsh * P.nsh * P.nimg;
+  if (lut_n > (int64_t)1 << 31) return fail(HFX_ERR_UNSUPPORTED, "block lookup table too large");
+  P.lut.assign(lut_n, -1);
+  auto imgidx = [&](int a, int b, int c) {
+    if (std::abs(a) > P.imgR[0] || std::abs(b) > P.imgR[1] || std::abs(c) > P.imgR[2]) return -1;
+    return ((a + P.imgR[0]) * (2 * P.imgR[1] + 1) + (b + P.imgR[1])) * (2 * P.imgR[2] + 1) + (c + P.imgR[2]);
+  };
+  P.blocks.resize(nb);
+  P.blk_IJ.resize(nb);
+  P.blk_off.resize(nb + 1);
+  P.blk_coff.resize(nb + 1);
+  int64_t off = 0, coff = 0;
+  for (int64_t i = 0; i < nb; ++i) {
+    const Key &k = keys[i];
+    hfx_block &b = P.blocks[i];
+    b.I = k.I;
+    b.J = k.J;
+    b.img[0] = k.a;
+    b.img[1] = k.b;
+    b.img[2] = k.c;
+    b.pad = 0;
+    b.offset = off;
+    P.blk_IJ[i] = make_int2(k.I, k.J);
+    P.blk_off[i] = off;
+    P.blk_coff[i] = coff;
+    off += nfunc_host(P.sh_l[k.I], P.sph) * nfunc_host(P.sh_l[k.J], P.sph);
+    coff += ncart(P.sh_l[k.I]) * ncart(P.sh_l[k.J]);
+    P.lut[((int64_t)k.I * P.nsh + k.J) * P.nimg + imgidx(k.a, k.b, k.c)] = (int32_t)i;
+  }
+  P.blk_off[nb] = off;
+  P.blk_coff[nb] = coff;
+  P.nnz = off;
+  P.nnz_c = coff;
+  P.partner.resize(nb);
+  P.canon.resize(nb);
+  for (int64_t i = 0; i < nb; ++i) {
+    const Key &k = keys[i];
+    int pi = imgidx(-k.a, -k.b, -k.c);
+    P.partner[i] = pi < 0 ? -1 : P.lut[((int64_t)k.J * P.nsh + k.I) * P.nimg + pi];
+    if (P.partner[i] < 0) return fail(HFX_ERR_DEVICE, "internal: pattern is not symmetric");
+    P.canon[i] = (k.I < k.J || (k.I == k.J && lexpos(k.a, k.b, k.c))) ? 1 : 0;
+  }
+
+  // ---- unique pairs in evaluation orientation (la >= lb), class-sorted
+  struct PairRec {
+    int A, B, a, b, c, cls, blk, nsig;
+  };
+  std::vector<PairRec> prs;
+  for (int64_t i = 0; i < nb; ++i) {
+    if (!P.canon[i]) continue;
+    const Key &k = keys[i];
+    PairRec r;
+    if (P.sh_l[k.I] >= P.sh_l[k.J]) {
+      r = {k.I, k.J, k.a, k.b, k.c, 0, (int)i, 0};
+    } else {
+      r = {k.J, k.I, -k.a, -k.b, -k.c, 0, (int)P.partner[i], 0};
+    }
+    r.cls = pair_class(P.sh_l[r.A], P.sh_l[r.B]);
+    prs.push_back(r);
+  }
+  if (prs.size() >= kMaxPairs) return fail(HFX_ERR_UNSUPPORTED, "too many shell pairs for the quartet encoding");
+  // primitive pairs per unique pair, sorted by a magnitude bound
+  struct PPRec {
+    double v[kPP];
+    double bound;
+  };
+  std::vector<std::vector<PPRec>> ppr(prs.size());
+  const double pi = 3.14159265358979323846;
+  for (size_t q = 0; q < prs.size(); ++q) {
+    PairRec &r = prs[q];
+    double RA[3], RB[3], t[3] = {0, 0, 0};
+    if (P.periodic) lattice_vec(P, r.a, r.b, r.c, t);
+    for (int k = 0; k < 3; ++k) {
+      RA[k] = P.sh_xyz[3 * r.A + k];
+      RB[k] = P.sh_xyz[3 * r.B + k] + t[k];
+    }
+    double AB2 = 0.0;
+    for (int k = 0; k < 3; ++k) AB2 += (RA[k] - RB[k]) * (RA[k] - RB[k]);
+    const int la = P.sh_l[r.A], lb = P.sh_l[r.B];
+    for (int ia = 0; ia < P.sh_np[r.A]; ++ia)
+      for (int ib = 0; ib < P.sh_np[r.B]; ++ib) {
+        const double al = P.ex[P.sh_poff[r.A] + ia], be = P.ex[P.sh_poff[r.B] + ib];
+        const double z = al + be;
+        PPRec e;
+        e.v[0] = z;
+        double PA = 0.0, PB = 0.0;
+        for (int k = 0; k < 3; ++k) {
+          const double Pk = (al * RA[k] + be * RB[k]) / z;
+          e.v[1 + k] = Pk;
+          e.v[4 + k] = Pk - RA[k];
+          PA += (Pk - RA[k]) * (Pk - RA[k]);
+          PB += (Pk - RB[k]) * (Pk - RB[k]);
+        }
+        e.v[7] = P.cn[P.sh_poff[r.A] + ia] * P.cn[P.sh_poff[r.B] + ib] * std::exp(-al * be / z * AB2);
+        // sqrt of the s-type self-repulsion of the product, widened by the
+        // polynomial prefactors of the angular parts
+        const double rz = 1.0 / std::sqrt(z);
+        e.bound = std::fabs(e.v[7]) * std::pow(pi, 1.25) * std::pow(2.0, 0.25) * std::pow(z, -1.25) *
+                  std::pow(1.0 + std::sqrt(PA) + rz, la) * std::pow(1.0 + std::sqrt(PB) + rz, lb);
+        ppr[q].push_back(e);
+      }
+    std::stable_sort(ppr[q].begin(), ppr[q].end(), [](const PPRec &x, const PPRec &y) { return x.bound > y.bound; });
+    int ns = 0;
+    for (auto &e : ppr[q]) ns += e.bound >= kPrimDrop;
+    r.nsig = ns;
+  }
+  std::vector<int> order(prs.size());
+  for (size_t q = 0; q < prs.size(); ++q) order[q] = (int)q;
+  std::stable_sort(order.begin(), order.end(), [&](int x, int y) {
+    if (prs[x].cls != prs[y].cls) return prs[x].cls < prs[y].cls;
+    return prs[x].nsig > prs[y].nsig;
+  });
+  const int npairs = (int)prs.size();
+  P.pr_info.resize(npairs);
+  P.pr_geom.assign((size_t)npairs * 8, 0.0);
+  P.pr_pp.resize(npairs);
+  P.pr_npp.resize(npairs);
+  P.block_pair.assign(nb, -1);
+  for (int c = 0; c <= kNPairClass; ++c) P.class_start[c] = 0;
+  int64_t ppoff = 0;
+  for (int q = 0; q < npairs; ++q) {
+    const PairRec &r = prs[order[q]];
+    const bool self = (r.A == r.B && r.a == 0 && r.b == 0 && r.c == 0);
+    P.pr_info[q] = make_int4(r.A, r.B, pack_img8(r.a, r.b, r.c), self ? 1 : 0);
+    double t[3] = {0, 0, 0};
+    if (P.periodic) lattice_vec(P, r.a, r.b, r.c, t);
+    double ab2 = 0.0;
+    for (int k = 0; k < 3; ++k) {
+      const double RA = P.sh_xyz[3 * r.A + k], RB = P.sh_xyz[3 * r.B + k] + t[k];
+      P.pr_geom[8 * q + k] = RA - RB;
+      P.pr_geom[8 * q + 3 + k] = 0.5 * (RA + RB);
+      ab2 += (RA - RB) * (RA - RB);
+    }
+    P.pr_geom[8 * q + 6] = 0.5 * std::sqrt(ab2);
+    const auto &v = ppr[order[q]];
+    P.pr_pp[q] = make_int2((int)ppoff, r.nsig);
+    P.pr_npp[q] = (int)v.size();
+    for (auto &e : v)
+      for (int k = 0; k < kPP; ++k) P.pp.push_back(e.v[k]);
+    ppoff += (int64_t)v.size();
+    P.block_pair[r.blk] = q;
+    P.block_pair[P.partner[r.blk]] = q;
+    P.class_start[r.cls + 1]++;
+  }
+  if (ppoff >= (int64_t)INT32_MAX) return fail(HFX_ERR_UNSUPPORTED, "too many primitive pairs");
+  for (int c = 0; c < kNPairClass; ++c) P.class_start[c + 1] += P.class_start[c];
+
+  // ---- screening work items: (region, bra pair), regions (cb >= ck)
+  for (int cb = 0; cb < kNPairClass; ++cb)
+    for (int ck = 0; ck <= cb; ++ck) {
+      const int r = region_of(cb, ck);
+      P.region_item[r] = (int64_t)P.items.size();
+      if (P.class_start[ck + 1] == P.class_start[ck]) continue;
+      for (int p = P.class_start[cb]; p < P.class_start[cb + 1]; ++p) P.items.push_back(make_int2(r, p));
+    }
+  P.region_item[kNQuartetClass] = (int64_t)P.items.size();
+  return HFX_OK;
+}
+
+template <typename T>
+hipError_t upload(hfx_plan_s &P, T **dst, const std::vector<T> &src) {
+  hipError_t e = P.mem.alloc(dst, src.size());
+  if (e != hipSuccess) return e;
+  if (!src.empty()) e = hipMemcpyAsync(*dst, src.data(), src.size() * sizeof(T), hipMemcpyHostToDevice, P.stream);
+  return e;
+}
+
+hfx_status upload_plan(hfx_plan_s &P) {
+  HIPCHK(upload(P, &P.d_sh_xyz, P.sh_xyz));
+  HIPCHK(upload(P, &P.d_sh_l, P.sh_l));
+  HIPCHK(upload(P, &P.d_pr_info, P.pr_info));
+  HIPCHK(upload(P, &P.d_pr_geom, P.pr_geom));
+  HIPCHK(upload(P, &P.d_pr_pp, P.pr_pp));
+  HIPCHK(upload(P, &P.d_pr_npp, P.pr_npp));
+  HIPCHK(P.mem.alloc(&P.d_pr_Q, P.pr_info.size()));
+  HIPCHK(upload(P, &P.d_pp, P.pp));
+  HIPCHK(upload(P, &P.d_lut, P.lut));
+  HIPCHK(upload(P, &P.d_blk_IJ, P.blk_IJ));
+  HIPCHK(upload(P, &P.d_blk_off, P.blk_off));
+  HIPCHK(upload(P, &P.d_blk_coff, P.blk_coff));
+  HIPCHK(upload(P, &P.d_partner, P.partner));
+  HIPCHK(upload(P, &P.d_canon, P.canon));
+  HIPCHK(P.mem.alloc(&P.d_pmax, P.blocks.size()));
+  HIPCHK(P.mem.alloc(&P.d_pglob, 1));
+  HIPCHK(P.mem.alloc(&P.d_Dc, (size_t)P.nnz_c));
+  HIPCHK(P.mem.alloc(&P.d_K4, (size_t)P.nnz_c));
+  HIPCHK(upload(P, &P.d_boys, boys_table()));
+  HIPCHK(upload(P, &P.d_items, P.items));
+  HIPCHK(P.mem.alloc(&P.d_counts, P.items.size()));
+  HIPCHK(P.mem.alloc(&P.d_offsets, P.items.size() + 1));
+  std::vector<int32_t> cs(P.class_start, P.class_start + kNPairClass + 1);
+  HIPCHK(upload(P, &P.d_class_start, cs));
+  HIPCHK(P.mem.alloc(&P.d_err, 2));
+  HIPCHK(P.mem.alloc(&P.d_nprim, kNQuartetClass));
+  P.scan_tmp_bytes = 0;
+  HIPCHK(scan_counts(P.d_counts, P.d_offsets, (int64_t)std::max<size_t>(P.items.size(), 1), nullptr,
+                     P.scan_tmp_bytes, P.stream));
+  HIPCHK(P.mem.alloc((char **)&P.d_scan_tmp, P.scan_tmp_bytes));
+
+  DevSys &s = P.ds;
+  s.sh_xyz = P.d_sh_xyz;
+  s.sh_l = P.d_sh_l;
+  s.nsh = P.nsh;
+  s.pr_info = P.d_pr_info;
+  s.pr_geom = P.d_pr_geom;
+  s.pr_pp = P.d_pr_pp;
+  s.pr_npp = P.d_pr_npp;
+  s.pr_Q = P.d_pr_Q;
+  s.npairs = (int32_t)P.pr_info.size();
+  s.pp = P.d_pp;
+  s.lut = P.d_lut;
+  for (int k = 0; k < 3; ++k) s.imgR[k] = P.imgR[k];
+  s.nimg = P.nimg;
+  s.blk_coff = P.d_blk_coff;
+  s.pmax = P.d_pmax;
+  s.pmax_global = P.d_pglob;
+  s.periodic = P.periodic ? 1 : 0;
+  std::memcpy(s.lat, P.lat, sizeof(s.lat));
+  std::memcpy(s.rec, P.rec, sizeof(s.rec));
+  std::memcpy(s.recn, P.recn, sizeof(s.recn));
+  s.cutoff = P.cutoff;
+  s.op = P.op;
+  s.omega2 = P.omega * P.omega;
+  s.tau = P.tau;
+  s.boys = P.d_boys;
+  HIPCHK(hipStreamSynchronize(P.stream));
+  return HFX_OK;
+}
+
+// live plans: a destroyed handle is rejected without being dereferenced
+std::mutex g_plans_mu;
+std::unordered_set<const hfx_plan_s *> g_plans;
+
+bool valid_plan(hfx_plan_t p) {
+  std::lock_guard<std::mutex> lk(g_plans_mu);
+  return p && g_plans.count(p) && p->magic == kMagic;
+}
+
+hfx_status run_schwarz(hfx_plan_s &P) {
+  for (int c = 0; c < kNPairClass; ++c)
+    launch_schwarz(c, P.op, P.ds, P.class_start[c], P.class_start[c + 1], P.stream);
+  HIPCHK(hipGetLastError());
+  P.schwarz_done = true;
+  return HFX_OK;
+}
+
+// ----------------------------------------------------------------- FLOPs
+// Algorithmic floating-point operations of the implemented recursions
+// (FMA = 2, add/mul/div/sqrt = 1), per primitive quartet and per contracted
+// quartet of a class; mirrors os_hgp.hpp term by term.
+void class_flops(int la, int lb, int lc, int ld, int op, double &per_prim, double &per_quartet) {
+  const int EB = la + lb, FK = lc + ld, L = EB + FK;
+  auto cart = [](int l, int c, int &x, int &y, int &z) {
+    int a = 0;
+    while ((a + 1) * (a + 2) / 2 <= c) ++a;
+    z = c - a * (a + 1) / 2;
+    x = l - a;
+    y = a - z;
+  };
+  double f = 0.0;
+  f += 34.0;                                   // prefactor, rho, T, W-P, W-Q, 1/(2 zeta) ...
+  double boys = 23.0 + (L > 0 ? 22.0 + 3.0 * L : 0.0);
+  f += (op == 1) ? 2 * boys + 8.0 + 4.0 * (L + 1) : boys;
+  f += (L + 1);                                // G *= pref
+  for (int e = 1; e <= EB; ++e)
+    for (int c = 0; c < ncart(e); ++c) {
+      int x, y, z;
+      cart(e, c, x, y, z);
+      int v[3] = {x, y, z};
+      int i = x > 0 ? 0 : (y > 0 ? 1 : 2);
+      int n1 = v[i] - 1;
+      f += (L - e + 1) * (3.0 + (n1 > 0 ? 5.0 : 0.0));
+    }
+  for (int fl = 1; fl <= FK; ++fl) {
+    int elo = std::max(0, la - (FK - fl));
+    for (int d = 0; d < ncart(fl); ++d) {
+      int x, y, z;
+      cart(fl, d, x, y, z);
+      int w[3] = {x, y, z};
+      int i = x > 0 ? 0 : (y > 0 ? 1 : 2);
+      int nf = w[i] - 1;
+      for (int e = elo; e <= EB; ++e)
+        for (int c = 0; c < ncart(e); ++c) {
+          int ux, uy, uz;
+          cart(e, c, ux, uy, uz);
+          int u[3] = {ux, uy, uz};
+          f += (FK - fl + 1) * (3.0 + (nf > 0 ? 5.0 : 0.0) + (u[i] > 0 ? 3.0 : 0.0));
+        }
+    }
+  }
+  const int NE = noff(EB + 1) - noff(la), NF = noff(FK + 1) - noff(lc);
+  f += NE * NF;  // accumulate
+  per_prim = f;
+  double g = 0.0;
+  // HRR: one FMA per transferred element
+  for (int b = 1; b <= lb; ++b) g += 2.0 * ncart(b) * (noff(EB - b + 1) - noff(la)) * NF;
+  for (int d = 1; d <= ld; ++d) g += 2.0 * ncart(d) * (noff(FK - d + 1) - noff(lc)) * ncart(la) * ncart(lb);
+  const int NOUT = ncart(la) * ncart(lb) * ncart(lc) * ncart(ld);
+  g += 8.0 * NOUT;  // four digest contractions, one FMA per integral each
+  g += 2.0 * (ncart(la) * ncart(lc) + ncart(lb) * ncart(lc) + ncart(la) * ncart(ld) + ncart(lb) * ncart(ld));
+  per_quartet = g;
+}
+
+}  // namespace
+
+// =================================================================== ABI
+extern "C" {
+
+const char *hfx_last_error(void) { return g_err.c_str(); }
+
+hfx_status hfx_footprint(const hfx_system *sys, size_t *device_bytes, size_t *list_bytes_per_quartet) {
+  hfx_status st = validate(sys);
+  if (st != HFX_OK) return st;
+  if (!device_bytes) return fail(HFX_ERR_INVALID, "device_bytes is NULL");
+  hfx_plan_s P;
+  st = build_host(P, sys);
+  if (st != HFX_OK) return st;
+  size_t b = 0;
+  b += P.sh_xyz.size() * 8 + P.sh_l.size() * 4;
+  b += P.pr_info.size() * (sizeof(int4) + 8 * 8 + sizeof(int2) + 4 + 8);
+  b += P.pp.size() * 8 + P.lut.size() * 4;
+  b += P.blocks.size() * (sizeof(int2) + 8 + 8 + 4 + 1 + 8) + 16;
+  b += (size_t)P.nnz_c * 16;
+  b += (size_t)kBoysRows * kBoysCols * 8;
+  b += P.items.size() * (sizeof(int2) + 4 + 8) + 8;
+  *device_bytes = b;
+  if (list_bytes_per_quartet) *list_bytes_per_quartet = sizeof(uint64_t);
+  return HFX_OK;
+}
+
+hfx_status hfx_plan(const hfx_system *sys, void *stream, hfx_plan_t *out) {
+  if (!out) return fail(HFX_ERR_INVALID, "out is NULL");
+  *out = nullptr;
+  hfx_status st = validate(sys);
+  if (st != HFX_OK) return st;
+  hfx_plan_s *P = new hfx_plan_s();
+  P->stream = (hipStream_t)stream;
+  st = build_host(*P, sys);
+  if (st == HFX_OK) st = upload_plan(*P);
+  if (st != HFX_OK) {
+    P->mem.release();
+    P->magic = 0;
+    delete P;
+    return st;
+  }
+  {
+    std::lock_guard<std::mutex> lk(g_plans_mu);
+    g_plans.insert(P);
+  }
+  *out = P;
+  return HFX_OK;
+}
+
+hfx_status hfx_pattern(hfx_plan_t plan, int64_t *n_blocks, int64_t *nnz, const hfx_block **blocks) {
+  if (!valid_plan(plan)) return fail(HFX_ERR_STATE, "invalid or destroyed plan");
+  if (n_blocks) *n_blocks = (int64_t)plan->blocks.size();
+  if (nnz) *nnz = plan->nnz;
+  if (blocks) *blocks = plan->blocks.data();
+  return HFX_OK;
+}
+
+hfx_status hfx_schwarz(hfx_plan_t plan, double *q_host, int64_t *n_pairs) {
+  if (!valid_plan(plan)) return fail(HFX_ERR_STATE, "invalid or destroyed plan");
+  hfx_plan_s &P = *plan;
+  hfx_status st = run_schwarz(P);
+  if (st != HFX_OK) return st;
+  if (n_pairs) *n_pairs = (int64_t)P.pr_info.size();
+  if (q_host) {
+    std::vector<double> q(P.pr_info.size());
+    if (!q.empty()) HIPCHK(hipMemcpyAsync(q.data(), P.d_pr_Q, q.size() * 8, hipMemcpyDeviceToHost, P.stream));
+    HIPCHK(hipStreamSynchronize(P.stream));
+    for (size_t b = 0; b < P.blocks.size(); ++b) q_host[b] = q[P.block_pair[b]];
+  }
+  return HFX_OK;
+}
+
+static hfx_status build_one(hfx_plan_s &P, const double *d_dev, double *k_dev, uint32_t flags, hfx_build_info *info) {
+  if (!d_dev || !k_dev) return fail(HFX_ERR_INVALID, "D or K pointer is NULL");
+  if (!P.schwarz_done) {
+    hfx_status st = run_schwarz(P);
+    if (st != HFX_OK) return st;
+  }
+  const bool timing = (flags & HFX_TIMING) != 0;
+  hipEvent_t ev[5];
+  if (timing)
+    for (auto &e : ev) HIPCHK(hipEventCreate(&e));
+  if (timing) HIPCHK(hipEventRecord(ev[0], P.stream));
+  // density -> Cartesian blocks, P_max
+  launch_zero_u64(P.d_pglob, 1, P.stream);
+  launch_density(P.ds, (int64_t)P.blocks.size(), P.d_blk_IJ, P.d_blk_off, P.d_partner, P.d_canon, P.sph, d_dev, P.d_Dc,
+                 P.stream);
+  if (timing) HIPCHK(hipEventRecord(ev[1], P.stream));
+  // screen: count, scan, fill
+  const int64_t nitems = (int64_t)P.items.size();
+  launch_zero_u64((unsigned long long *)P.d_err, 1, P.stream);
+  launch_screen(P.ds, P.d_items, nitems, P.d_class_start, P.d_counts, P.d_offsets, nullptr, P.d_err, false, P.stream);
+  std::vector<int64_t> offs(nitems + 1, 0);
+  if (nitems > 0) {
+    HIPCHK(scan_counts(P.d_counts, P.d_offsets, nitems, P.d_scan_tmp, P.scan_tmp_bytes, P.stream));
+    HIPCHK(hipMemcpyAsync(offs.data(), P.d_offsets, (nitems + 1) * 8, hipMemcpyDeviceToHost, P.stream));
+  }
+  HIPCHK(hipStreamSynchronize(P.stream));
+  for (int r = 0; r <= kNQuartetClass; ++r) P.region_q[r] = offs[P.region_item[r]];
+  P.nq_total = offs[nitems];
+  if (P.nq_total > P.list_cap) {
+    if (P.d_list) HIPCHK(hipFree(P.d_list));
+    P.d_list = nullptr;
+    P.list_cap = 0;
+    int64_t cap = P.nq_total + P.nq_total / 8 + 1024;
+    hipError_t e = hipMalloc((void **)&P.d_list, (size_t)cap * sizeof(uint64_t));
+    if (e != hipSuccess) return fail(HFX_ERR_OOM, "quartet list allocation failed");
+    P.list_cap = cap;
+  }
+  launch_screen(P.ds, P.d_items, nitems, P.d_class_start, P.d_counts, P.d_offsets, P.d_list, P.d_err, true, P.stream);
+  if (timing) HIPCHK(hipEventRecord(ev[2], P.stream));
+  // ERI + digest
+  launch_zero(P.d_K4, P.nnz_c, P.stream);
+  launch_zero_u64(P.d_nprim, kNQuartetClass, P.stream);
+  for (int cb = kNPairClass - 1; cb >= 0; --cb)
+    for (int ck = cb; ck >= 0; --ck) {
+      const int r = region_of(cb, ck);
+      const int64_t n = P.region_q[r + 1] - P.region_q[r];
+      if (n > 0) launch_eri(cb, ck, P.op, P.ds, P.d_list + P.region_q[r], n, P.d_Dc, P.d_K4, P.d_nprim + r, P.stream);
+    }
+  if (timing) HIPCHK(hipEventRecord(ev[3], P.stream));
+  launch_finalize(P.ds, (int64_t)P.blocks.size(), P.d_blk_IJ, P.d_blk_off, P.d_partner, P.sph, P.d_K4, k_dev, P.stream);
+  if (timing) HIPCHK(hipEventRecord(ev[4], P.stream));
+  HIPCHK(hipGetLastError());
+  if ((flags & (HFX_SYNC | HFX_TIMING)) || info) {
+    HIPCHK(hipStreamSynchronize(P.stream));
+    int32_t err = 0;
+    HIPCHK(hipMemcpy(&err, P.d_err, 4, hipMemcpyDeviceToHost));
+    if (err) return fail(HFX_ERR_UNSUPPORTED, "a ket translation exceeds the quartet encoding range");
+  }
+  if (info) {
+    std::memset(info, 0, sizeof(*info));
+    unsigned long long np[kNQuartetClass];
+    HIPCHK(hipMemcpy(np, P.d_nprim, sizeof(np), hipMemcpyDeviceToHost));
+    info->n_quartets = P.nq_total;
+    double fl = 0.0;
+    for (int cb = 0; cb < kNPairClass; ++cb)
+      for (int ck = 0; ck <= cb; ++ck) {
+        const int r = region_of(cb, ck);
+        info->n_quartets_class[r] = P.region_q[r + 1] - P.region_q[r];
+        info->n_prim_quartets += (int64_t)np[r];
+        double fp, fq;
+        class_flops(class_la(cb), class_lb(cb), class_la(ck), class_lb(ck), P.op, fp, fq);
+        fl += fp * (double)np[r] + fq * (double)info->n_quartets_class[r];
+      }
+    info->flops = fl;
+    if (timing) {
+      float ms;
+      HIPCHK(hipEventElapsedTime(&ms, ev[0], ev[1]));
+      info->ms_density = ms;
+      HIPCHK(hipEventElapsedTime(&ms, ev[1], ev[2]));
+      info->ms_screen = ms;
+      HIPCHK(hipEventElapsedTime(&ms, ev[2], ev[3]));
+      info->ms_eri = ms;
+      HIPCHK(hipEventElapsedTime(&ms, ev[3], ev[4]));
+      info->ms_finalize = ms;
+      HIPCHK(hipEventElapsedTime(&ms, ev[0], ev[4]));
+      info->ms_total = ms;
+    }
+  }
+  if (timing)
+    for (auto &e : ev) (void)hipEventDestroy(e);
+  return HFX_OK;
+}
+
+hfx_status hfx_build_K(hfx_plan_t plan, const double *d_dev, double *k_dev, uint32_t flags, hfx_build_info *info) {
+  if (!valid_plan(plan)) return fail(HFX_ERR_STATE, "invalid or destroyed plan");
+  return build_one(*plan, d_dev, k_dev, flags, info);
+}
+
+hfx_status hfx_build_K_multi(int32_t n, const hfx_plan_t *plans, const double *const *d_dev, double *const *k_dev,
+                             uint32_t flags, hfx_build_info *info) {
+  if (n < 0 || (n > 0 && (!plans || !d_dev || !k_dev))) return fail(HFX_ERR_INVALID, "bad arguments");
+  for (int i = 0; i < n; ++i)
+    if (!valid_plan(plans[i])) return fail(HFX_ERR_STATE, "invalid or destroyed plan");
+  for (int i = 0; i < n; ++i) {
+    hfx_status st = build_one(*plans[i], d_dev[i], k_dev[i], flags, nullptr);
+    if (st != HFX_OK) return st;
+  }
+  if (info) std::memset(info, 0, sizeof(*info));
+  return HFX_OK;
+}
+
+hfx_status hfx_export(hfx_plan_t plan, int32_t what, void *host, int64_t *n) {
+  if (!valid_plan(plan)) return fail(HFX_ERR_STATE, "invalid or destroyed plan");
+  if (!n) return fail(HFX_ERR_INVALID, "n is NULL");
+  hfx_plan_s &P = *plan;
+  switch (what) {
+    case 0:
+      *n = (int64_t)P.blocks.size();
+      if (host && *n) {
+        HIPCHK(hipStreamSynchronize(P.stream));
+        HIPCHK(hipMemcpy(host, P.d_pmax, *n * 8, hipMemcpyDeviceToHost));
+      }
+      return HFX_OK;
+    case 1:
+      *n = P.nq_total;
+      if (host && *n) {
+        HIPCHK(hipStreamSynchronize(P.stream));
+        HIPCHK(hipMemcpy(host, P.d_list, *n * 8, hipMemcpyDeviceToHost));
+      }
+      return HFX_OK;
+    case 2: {
+      *n = (int64_t)P.pr_info.size();
+      if (host) {
+        int32_t *o = (int32_t *)host;
+        for (int64_t q = 0; q < *n; ++q) {
+          int a, b, c;
+          unpack_img8(P.pr_info[q].z, a, b, c);
+          const int cls = pair_class(P.sh_l[P.pr_info[q].x], P.sh_l[P.pr_info[q].y]);
+          int32_t row[6] = {P.pr_info[q].x, P.pr_info[q].y, a, b, c, cls};
+          std::memcpy(o + 6 * q, row, sizeof(row));
+        }
+      }
+      return HFX_OK;
+    }
+    case 3:
+      *n = (int64_t)P.pr_info.size();
+      if (host && *n) {
+        HIPCHK(hipStreamSynchronize(P.stream));
+        HIPCHK(hipMemcpy(host, P.d_pr_Q, *n * 8, hipMemcpyDeviceToHost));
+      }
+      return HFX_OK;
+    default:
+      return fail(HFX_ERR_INVALID, "unknown export");
+  }
+}
+
+hfx_status hfx_plan_destroy(hfx_plan_t plan) {
+  if (!valid_plan(plan)) return fail(HFX_ERR_STATE, "invalid or destroyed plan");
+  {
+    std::lock_guard<std::mutex> lk(g_plans_mu);
+    g_plans.erase(plan);
+  }
+  (void)hipStreamSynchronize(plan->stream);
+  if (plan->d_list) (void)hipFree(plan->d_list);
+  plan->mem.release();
+  plan->magic = 0;
+  delete plan;
+  return HFX_OK;
+}
+
+}  // extern "C"

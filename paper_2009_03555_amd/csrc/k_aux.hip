@@ -1,0 +1,305 @@
+// Bandwidth-bound kernels around the ERI phase: density transform and
+// P_max (Eq. dmscreening), quartet screening and compaction (Eq. schwarz
+// times P_scr, 8-fold unique enumeration), K finalisation, fills.
+#include <hipcub/hipcub.hpp>
+
+#include "launchers.hpp"
+
+namespace hfx {
+
+// --------------------------------------------------------- dispatchers
+void launch_eri(int cb, int ck, int op, const DevSys &s, const uint64_t *list, int64_t nq, const double *Dc,
+                double *K4, unsigned long long *nprim, hipStream_t st) {
+  typedef void (*fn)(int, const DevSys &, const uint64_t *, int64_t, const double *, double *, unsigned long long *,
+                     hipStream_t);
+  static const fn table[kNQuartetClass] = {
+      launch_eri_r00, launch_eri_r10, launch_eri_r11, launch_eri_r20, launch_eri_r21, launch_eri_r22,
+      launch_eri_r30, launch_eri_r31, launch_eri_r32, launch_eri_r33, launch_eri_r40, launch_eri_r41,
+      launch_eri_r42, launch_eri_r43, launch_eri_r44, launch_eri_r50, launch_eri_r51, launch_eri_r52,
+      launch_eri_r53, launch_eri_r54, launch_eri_r55};
+  if (cb < 0 || cb >= kNPairClass || ck < 0 || ck > cb) return;
+  table[region_of(cb, ck)](op, s, list, nq, Dc, K4, nprim, st);
+}
+
+void launch_schwarz(int cb, int op, const DevSys &s, int p0, int p1, hipStream_t st) {
+  switch (cb) {
+    case 0: launch_schwarz_c0(op, s, p0, p1, st); break;
+    case 1: launch_schwarz_c1(op, s, p0, p1, st); break;
+    case 2: launch_schwarz_c2(op, s, p0, p1, st); break;
+    case 3: launch_schwarz_c3(op, s, p0, p1, st); break;
+    case 4: launch_schwarz_c4(op, s, p0, p1, st); break;
+    case 5: launch_schwarz_c5(op, s, p0, p1, st); break;
+    default: break;
+  }
+}
+
+// ------------------------------------------------- spherical transform
+// Rows: real solid harmonics m = -2..2; columns xx, xy, xz, yy, yz, zz.
+__constant__ double kSphD[5][6] = {
+    {0.0, 1.7320508075688772935, 0.0, 0.0, 0.0, 0.0},
+    {0.0, 0.0, 0.0, 0.0, 1.7320508075688772935, 0.0},
+    {-0.5, 0.0, 0.0, -0.5, 0.0, 1.0},
+    {0.0, 0.0, 1.7320508075688772935, 0.0, 0.0, 0.0},
+    {0.86602540378443864676, 0.0, 0.0, -0.86602540378443864676, 0.0, 0.0}};
+
+__device__ __forceinline__ int nfunc_dev(int l, int sph) { return (l == 2 && sph) ? 5 : (l + 1) * (l + 2) / 2; }
+// T[m][a] of shell l (identity unless spherical d)
+__device__ __forceinline__ double tmat(int l, int sph, int m, int a) {
+  if (l == 2 && sph) return kSphD[m][a];
+  return m == a ? 1.0 : 0.0;
+}
+
+__global__ void density_kernel(DevSys s, int64_t nblk, const int2 *__restrict__ blk_IJ,
+                               const int64_t *__restrict__ blk_off, const int32_t *__restrict__ partner,
+                               const uint8_t *__restrict__ canon, int sph, const double *__restrict__ D,
+                               double *__restrict__ Dc) {
+  const int64_t b = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (b >= nblk) return;
+  const int2 ij = blk_IJ[b];
+  const int li = s.sh_l[ij.x], lj = s.sh_l[ij.y];
+  const int ni = nfunc_dev(li, sph), nj = nfunc_dev(lj, sph);
+  const int ci = ncart(li), cj = ncart(lj);
+  const double *src = D + blk_off[b];
+  double *dst = Dc + s.blk_coff[b];
+  const bool ti = (li == 2 && sph), tj = (lj == 2 && sph);
+  double pm = 0.0;
+  for (int a = 0; a < ci; ++a)
+    for (int c = 0; c < cj; ++c) {
+      double v;
+      if (!ti && !tj) {
+        v = src[a * nj + c];
+      } else {
+        v = 0.0;
+        for (int m = 0; m < ni; ++m) {
+          const double tma = ti ? kSphD[m][a] : (m == a ? 1.0 : 0.0);
+          if (tma == 0.0) continue;
+          double r = 0.0;
+          for (int n = 0; n < nj; ++n) {
+            const double tnc = tj ? kSphD[n][c] : (n == c ? 1.0 : 0.0);
+            r += src[m * nj + n] * tnc;
+          }
+          v += tma * r;
+        }
+      }
+      dst[a * cj + c] = v;
+      pm = fmax(pm, fabs(v));
+    }
+  if (canon[b]) {
+    s.pmax[b] = pm;
+    s.pmax[partner[b]] = pm;
+    atomicMax(s.pmax_global, (unsigned long long)__double_as_longlong(pm));
+  }
+}
+
+void launch_density(const DevSys &s, int64_t nblk, const int2 *blk_IJ, const int64_t *blk_off,
+                    const int32_t *partner, const uint8_t *canon, int spherical, const double *D, double *Dc,
+                    hipStream_t st) {
+  if (nblk <= 0) return;
+  hipLaunchKernelGGL(density_kernel, dim3((unsigned)((nblk + 255) / 256)), dim3(256), 0, st, s, nblk, blk_IJ,
+                     blk_off, partner, canon, spherical, D, Dc);
+}
+
+// ------------------------------------------------------------ finalize
+__global__ void finalize_kernel(DevSys s, int64_t nblk, const int2 *__restrict__ blk_IJ,
+                                const int64_t *__restrict__ blk_off, const int32_t *__restrict__ partner,
+                                int sph, const double *__restrict__ K4, double *__restrict__ K) {
+  const int64_t b = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (b >= nblk) return;
+  const int2 ij = blk_IJ[b];
+  const int li = s.sh_l[ij.x], lj = s.sh_l[ij.y];
+  const int ni = nfunc_dev(li, sph), nj = nfunc_dev(lj, sph);
+  const int ci = ncart(li), cj = ncart(lj);
+  const double *k1 = K4 + s.blk_coff[b];
+  const double *k2 = K4 + s.blk_coff[partner[b]];  // (J, I, -n): ci x cj transposed
+  double kc[36];
+  for (int a = 0; a < ci; ++a)
+    for (int c = 0; c < cj; ++c) kc[a * cj + c] = k1[a * cj + c] + k2[c * ci + a];
+  double *dst = K + blk_off[b];
+  const bool ti = (li == 2 && sph), tj = (lj == 2 && sph);
+  for (int m = 0; m < ni; ++m)
+    for (int n = 0; n < nj; ++n) {
+      double v;
+      if (!ti && !tj) {
+        v = kc[m * cj + n];
+      } else {
+        v = 0.0;
+        for (int a = 0; a < ci; ++a) {
+          const double tma = ti ? kSphD[m][a] : (m == a ? 1.0 : 0.0);
+          if (tma == 0.0) continue;
+          double r = 0.0;
+          for (int c = 0; c < cj; ++c) {
+            const double tnc = tj ? kSphD[n][c] : (n == c ? 1.0 : 0.0);
+            r += kc[a * cj + c] * tnc;
+          }
+          v += tma * r;
+        }
+      }
+      dst[m * nj + n] = v;
+    }
+}
+
+void launch_finalize(const DevSys &s, int64_t nblk, const int2 *blk_IJ, const int64_t *blk_off,
+                     const int32_t *partner, int spherical, const double *K4, double *K, hipStream_t st) {
+  if (nblk <= 0) return;
+  hipLaunchKernelGGL(finalize_kernel, dim3((unsigned)((nblk + 255) / 256)), dim3(256), 0, st, s, nblk, blk_IJ,
+                     blk_off, partner, spherical, K4, K);
+}
+
+// --------------------------------------------------------------- fills
+__global__ void zero_kernel(double *p, int64_t n) {
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+    p[i] = 0.0;
+}
+__global__ void zero_u64_kernel(unsigned long long *p, int64_t n) {
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+    p[i] = 0ull;
+}
+void launch_zero(double *p, int64_t n, hipStream_t st) {
+  if (n <= 0) return;
+  int64_t blocks = (n + 255) / 256;
+  if (blocks > 8192) blocks = 8192;
+  hipLaunchKernelGGL(zero_kernel, dim3((unsigned)blocks), dim3(256), 0, st, p, n);
+}
+void launch_zero_u64(unsigned long long *p, int64_t n, hipStream_t st) {
+  if (n <= 0) return;
+  int64_t blocks = (n + 255) / 256;
+  if (blocks > 8192) blocks = 8192;
+  hipLaunchKernelGGL(zero_u64_kernel, dim3((unsigned)blocks), dim3(256), 0, st, p, n);
+}
+
+// ----------------------------------------------------------- screening
+__device__ __forceinline__ bool lex_nonneg(int a, int b, int c) {
+  return a > 0 || (a == 0 && (b > 0 || (b == 0 && c >= 0)));
+}
+
+__device__ __forceinline__ double pmax_at(const DevSys &s, int I, int J, int a, int b, int c) {
+  const int k = lookup(s, I, J, a, b, c);
+  return k < 0 ? 0.0 : s.pmax[k];
+}
+
+// Visit every ket translation G of the quartet (p | q^G) that survives
+// (Q_p * Q_q) * P_scr > tau.  For p == q only G >= 0 (lexicographic) is
+// visited: (p|p^G) and (p|p^-G) are one orbit of the permutation relations.
+template <typename F>
+__device__ __forceinline__ void visit_kept(const DevSys &s, int p, int q, double Qp, double Qq, double pglob,
+                                           int32_t *err, F &&emit) {
+  const double qq = Qp * Qq;
+  if (!(qq * pglob > s.tau)) return;
+  const int4 bi = s.pr_info[p], ki = s.pr_info[q];
+  int nB1, nB2, nB3, nD1, nD2, nD3;
+  unpack_img8(bi.z, nB1, nB2, nB3);
+  unpack_img8(ki.z, nD1, nD2, nD3);
+  const int A = bi.x, B = bi.y, C = ki.x, D = ki.y;
+  auto test = [&](int g1, int g2, int g3) {
+    double ps = pmax_at(s, A, C, g1, g2, g3);
+    ps = fmax(ps, pmax_at(s, A, D, g1 + nD1, g2 + nD2, g3 + nD3));
+    ps = fmax(ps, pmax_at(s, B, C, g1 - nB1, g2 - nB2, g3 - nB3));
+    ps = fmax(ps, pmax_at(s, B, D, g1 + nD1 - nB1, g2 + nD2 - nB2, g3 + nD3 - nB3));
+    const double bound = qq * ps;
+    return bound > s.tau;
+  };
+  if (!s.periodic) {
+    if (test(0, 0, 0)) emit(0, 0, 0);
+    return;
+  }
+  const double *gp = s.pr_geom + (int64_t)p * 8;
+  const double *gq = s.pr_geom + (int64_t)q * 8;
+  const double dx = gp[3] - gq[3], dy = gp[4] - gq[4], dz = gp[5] - gq[5];
+  const double R = gp[6] + gq[6] + s.cutoff + 1e-6;
+  int lo[3], hi[3];
+#pragma unroll
+  for (int i = 0; i < 3; ++i) {
+    const double f = s.rec[3 * i] * dx + s.rec[3 * i + 1] * dy + s.rec[3 * i + 2] * dz;
+    lo[i] = (int)ceil(f - R * s.recn[i]);
+    hi[i] = (int)floor(f + R * s.recn[i]);
+  }
+  for (int g1 = lo[0]; g1 <= hi[0]; ++g1)
+    for (int g2 = lo[1]; g2 <= hi[1]; ++g2)
+      for (int g3 = lo[2]; g3 <= hi[2]; ++g3) {
+        if (p == q && !lex_nonneg(g1, g2, g3)) continue;
+        const double tx = g1 * s.lat[0] + g2 * s.lat[3] + g3 * s.lat[6];
+        const double ty = g1 * s.lat[1] + g2 * s.lat[4] + g3 * s.lat[7];
+        const double tz = g1 * s.lat[2] + g2 * s.lat[5] + g3 * s.lat[8];
+        const double ex = dx - tx, ey = dy - ty, ez = dz - tz;
+        if (ex * ex + ey * ey + ez * ez > R * R) continue;
+        if (!test(g1, g2, g3)) continue;
+        if (g1 < -16 || g1 > 15 || g2 < -16 || g2 > 15 || g3 < -16 || g3 > 15) {
+          atomicOr(err, 1);
+          continue;
+        }
+        emit(g1, g2, g3);
+      }
+}
+
+__global__ __launch_bounds__(256) void screen_kernel(DevSys s, const int2 *__restrict__ items, int64_t nitems,
+                                                     const int32_t *__restrict__ class_start,
+                                                     int32_t *__restrict__ counts,
+                                                     const int64_t *__restrict__ offsets,
+                                                     uint64_t *__restrict__ out, int32_t *err, int fill) {
+  const int lane = threadIdx.x & 63;
+  const int64_t item = (int64_t)blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6);
+  if (item >= nitems) return;  // whole wave leaves together
+  const int2 it = items[item];
+  const int r = it.x, p = it.y;
+  int cb = 0;
+  while ((cb + 1) * (cb + 2) / 2 <= r) ++cb;
+  const int ck = r - cb * (cb + 1) / 2;
+  const int q0 = class_start[ck];
+  const int q1 = (cb == ck) ? p + 1 : class_start[ck + 1];
+  const double Qp = s.pr_Q[p];
+  const double pglob = __longlong_as_double((long long)*s.pmax_global);
+  int64_t running = fill ? offsets[item] : 0;
+  for (int qt = q0; qt < q1; qt += 64) {
+    const int q = qt + lane;
+    int cnt = 0;
+    double Qq = 0.0;
+    if (q < q1) {
+      Qq = s.pr_Q[q];
+      visit_kept(s, p, q, Qp, Qq, pglob, err, [&](int, int, int) { ++cnt; });
+    }
+    // wave-wide inclusive scan of cnt
+    int x = cnt;
+#pragma unroll
+    for (int o = 1; o < 64; o <<= 1) {
+      const int y = __shfl_up(x, o, 64);
+      if (lane >= o) x += y;
+    }
+    const int total = __shfl(x, 63, 64);
+    if (fill && q < q1 && cnt) {
+      int64_t pos = running + (x - cnt);
+      visit_kept(s, p, q, Qp, Qq, pglob, err, [&](int g1, int g2, int g3) {
+        out[pos++] = pack_quartet((uint32_t)p, (uint32_t)q, pack_img5(g1, g2, g3));
+      });
+    }
+    running += total;
+  }
+  if (!fill && lane == 0) counts[item] = (int32_t)running;
+}
+
+void launch_screen(const DevSys &s, const int2 *items, int64_t nitems, const int32_t *class_start,
+                   int32_t *counts, const int64_t *offsets, uint64_t *out, int32_t *err, bool fill,
+                   hipStream_t st) {
+  if (nitems <= 0) return;
+  const int64_t blocks = (nitems + 3) / 4;
+  hipLaunchKernelGGL(screen_kernel, dim3((unsigned)blocks), dim3(256), 0, st, s, items, nitems, class_start,
+                     counts, offsets, out, err, fill ? 1 : 0);
+}
+
+// exclusive scan: offsets[0] = 0, offsets[i+1] = sum_{k<=i} counts[k]
+struct I64Cast {
+  __host__ __device__ int64_t operator()(const int32_t &x) const { return (int64_t)x; }
+};
+
+hipError_t scan_counts(const int32_t *counts, int64_t *offsets, int64_t n, void *tmp, size_t &tmp_bytes,
+                       hipStream_t st) {
+  hipcub::TransformInputIterator<int64_t, I64Cast, const int32_t *> in(counts, I64Cast());
+  hipError_t e = hipSuccess;
+  if (tmp == nullptr) {
+    e = hipcub::DeviceScan::InclusiveSum(nullptr, tmp_bytes, in, offsets + 1, (int)n, st);
+    return e;
+  }
+  launch_zero_u64(reinterpret_cast<unsigned long long *>(offsets), 1, st);
+  return hipcub::DeviceScan::InclusiveSum(tmp, tmp_bytes, in, offsets + 1, (int)n, st);
+}
+
+}  // namespace hfx

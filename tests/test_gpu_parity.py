@@ -1,0 +1,199 @@
+"""GPU parity: the HIP path through the C ABI against the CPU oracle.
+
+Bars: K element by element within 1e-10 (FP64); Schwarz factors within
+1e-12 relative; P_max bit-identical; the quartet list equal as a set of
+canonical orbits, except quartets whose bound lies within 1e-12 relative of
+tau (there either decision is correct, both are FP64).
+"""
+import numpy as np
+import pytest
+
+import oracle
+import systems
+from tests.helpers import canonical_keys, gpu_quartet_instances, key_set, oracle_quartet_instances
+
+torch = pytest.importorskip("torch")
+hfx = pytest.importorskip("paper_2009_03555_amd.hfx")
+
+pytestmark = pytest.mark.gpu
+DEV = "cuda:0"
+TOL_FP64 = 1e-10
+
+
+def _density(system, blocks, iteration=0):
+    vals = systems.density_blocks(system, np.asarray(blocks, dtype=np.int64), iteration=iteration)
+    return np.concatenate([v.ravel() for v in vals]) if vals else np.zeros(0)
+
+
+class Case:
+    def __init__(self, system):
+        self.s = system
+        self.plan = hfx.Plan(system)
+        self.D = _density(system, self.plan.blocks)
+        self.Dd = torch.from_numpy(self.D).to(DEV)
+        self.Kd = torch.full_like(self.Dd, np.nan)
+        self.info = self.plan.build_K(self.Dd, self.Kd, flags=hfx.HFX_SYNC, info=True)
+        self.K = self.Kd.cpu().numpy()
+        self.o = oracle.Oracle(system)
+        self.o.schwarz()
+        self.o.set_density(self.D)
+
+
+def _tiny_cell(**kw):
+    kw.setdefault("seed", 77)
+    return systems.config2_diamond(n=(1, 1, 1), nprim=2, shells=(0, 1, 2), r_cut=4.6, **kw)
+
+
+@pytest.fixture(scope="module")
+def c1():
+    return Case(systems.config1_molecule())
+
+
+@pytest.fixture(scope="module")
+def cell():
+    return Case(_tiny_cell())
+
+
+def test_pattern_matches_oracle(c1, cell):
+    for c in (c1, cell):
+        assert np.array_equal(c.plan.blocks, c.o.blocks)
+        assert np.array_equal(c.plan.offsets, c.o.offsets)
+
+
+def test_schwarz_factors(c1, cell):
+    for c in (c1, cell):
+        q = c.plan.schwarz()
+        assert np.allclose(q, c.o.Q, rtol=1e-12, atol=0)
+
+
+def test_pmax_bit_identical_sp(c1):
+    pm = c1.plan.export(0)
+    assert np.array_equal(pm, c1.o.Pmax)
+
+
+def test_pmax_close_spd(cell):
+    pm = cell.plan.export(0)
+    assert np.allclose(pm, cell.o.Pmax, rtol=1e-15, atol=0)
+
+
+def test_K_config1_full(c1):
+    Kref, _ = c1.o.build_K()
+    err = np.max(np.abs(c1.K - Kref))
+    print(f"config1: {c1.info['n_quartets']} quartets, max|dK| = {err:.3e}")
+    assert err <= TOL_FP64
+
+
+def test_K_periodic_erfc_spd(cell):
+    Kref, _ = cell.o.build_K()
+    err = np.max(np.abs(cell.K - Kref))
+    print(f"tiny diamond cell: {cell.info['n_quartets']} quartets, max|dK| = {err:.3e}")
+    assert err <= TOL_FP64
+
+
+def _bounds_of(o, inst):
+    """Oracle bound (Q_IJ Q_KL) P_scr of each quartet instance (n,4,4)."""
+    keys = o.block_key_index()
+    out = np.zeros(len(inst))
+    for i, q in enumerate(inst):
+        (I, *_), (J, *nJ), (K, *nK), (L, *nL) = [tuple(int(v) for v in r) for r in q]
+        nJ, nK, nL = np.array(nJ), np.array(nK), np.array(nL)
+
+        def blk(X, Y, n):
+            return keys.get((X, Y) + tuple(int(v) for v in n), -1)
+
+        def pm(X, Y, n):
+            b = blk(X, Y, n)
+            return 0.0 if b < 0 else o.Pmax[b]
+        qij = o.Q[blk(I, J, nJ)]
+        qkl = o.Q[blk(K, L, nL - nK)]
+        ps = max(pm(I, K, nK), pm(I, L, nL), pm(J, K, nK - nJ), pm(J, L, nL - nJ))
+        out[i] = (qij * qkl) * ps
+    return out
+
+
+@pytest.mark.parametrize("which", ["c1", "cell"])
+def test_quartet_list_matches_oracle(which, c1, cell):
+    c = c1 if which == "c1" else cell
+    gl = hfx.unpack_quartets(c.plan.export(1))
+    pairs = c.plan.export(2)
+    gk = canonical_keys(gpu_quartet_instances(gl, pairs))
+    # unique: no orbit listed twice
+    assert len(key_set(gk)) == len(gk)
+    rows, bnd = c.o.quartets(gR=3)
+    ok = canonical_keys(oracle_quartet_instances(rows))
+    gs, os_ = key_set(gk), key_set(ok)
+    only_gpu = gs - os_
+    only_orc = os_ - gs
+    tau = c.s.tau
+    # every disagreement must sit at the threshold
+    if only_orc:
+        idx = [i for i, k in enumerate(map(tuple, ok.tolist())) if k in only_orc]
+        assert np.all(np.abs(bnd[idx] - tau) <= 1e-12 * tau), "oracle keeps quartets the GPU dropped"
+    if only_gpu:
+        inst = gpu_quartet_instances(gl, pairs)
+        idx = [i for i, k in enumerate(map(tuple, gk.tolist())) if k in only_gpu]
+        b = _bounds_of(c.o, inst[idx])
+        assert np.all(np.abs(b - tau) <= 1e-12 * tau), "GPU keeps quartets the oracle dropped"
+    print(f"{which}: {len(gs)} unique quartets, {len(only_gpu)}+{len(only_orc)} at the threshold")
+    assert c.info["n_quartets"] == len(gl)
+
+
+def test_cartesian_d_periodic():
+    c = Case(_tiny_cell(seed=78, spherical_d=False))
+    Kref, _ = c.o.build_K()
+    assert np.max(np.abs(c.K - Kref)) <= TOL_FP64
+
+
+def test_coulomb_molecule_with_d():
+    s = systems.random_cluster(6, 4242, edge=7.0, min_sep=1.8, nprim=2)
+    c = Case(s)
+    Kref, _ = c.o.build_K()
+    assert np.max(np.abs(c.K - Kref)) <= TOL_FP64
+
+
+def test_repeat_builds_agree(c1):
+    K2 = torch.zeros_like(c1.Dd)
+    c1.plan.build_K(c1.Dd, K2, flags=hfx.HFX_SYNC)
+    assert np.max(np.abs(K2.cpu().numpy() - c1.K)) <= 1e-13
+
+
+def test_zero_density_gives_zero():
+    s = systems.config1_molecule(seed=1234)
+    plan = hfx.Plan(s)
+    D = torch.zeros(plan.nnz, dtype=torch.float64, device=DEV)
+    K = torch.full_like(D, 7.0)
+    info = plan.build_K(D, K, flags=hfx.HFX_SYNC, info=True)
+    assert info["n_quartets"] == 0
+    assert torch.count_nonzero(K).item() == 0
+
+
+def test_huge_tau_screens_everything():
+    s = systems.config1_molecule().with_(tau=1e30)
+    plan = hfx.Plan(s)
+    D = torch.from_numpy(_density(s, plan.blocks)).to(DEV)
+    K = torch.full_like(D, 3.0)
+    info = plan.build_K(D, K, flags=hfx.HFX_SYNC, info=True)
+    assert info["n_quartets"] == 0
+    assert torch.count_nonzero(K).item() == 0
+
+
+def test_single_shell_atom():
+    s = systems.System(name="one_s", seed=5, atom_xyz=np.zeros((1, 3)),
+                       shell_atom=np.array([0], np.int32), shell_l=np.array([0], np.int32),
+                       shell_nprim=np.array([2], np.int32), prim_exp=np.array([0.5, 3.0]),
+                       prim_coef=np.array([0.4, 0.6]))
+    c = Case(s)
+    Kref, _ = c.o.build_K()
+    assert c.info["n_quartets"] == 1
+    assert np.max(np.abs(c.K - Kref)) <= TOL_FP64
+
+
+def test_destroyed_plan_is_rejected():
+    s = systems.config1_molecule()
+    plan = hfx.Plan(s)
+    h = plan.handle.value
+    plan.destroy()
+    D = torch.zeros(plan.nnz, dtype=torch.float64, device=DEV)
+    st = hfx.lib().hfx_build_K(hfx.ctypes.c_void_p(h), hfx.ctypes.c_void_p(D.data_ptr()),
+                               hfx.ctypes.c_void_p(D.data_ptr()), 0, None)
+    assert st == hfx.HFX_ERR_STATE
