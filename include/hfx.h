@@ -110,6 +110,8 @@ typedef struct {
   int64_t n_fp32_quartets;                /* quartets taken on the FP32 path */
   double flops;                           /* algorithmic FLOPs of the ERI phase */
   double ms_density, ms_screen, ms_eri, ms_finalize, ms_total; /* HFX_TIMING */
+  double ms_class[HFX_N_CLASSES];         /* HFX_TIMING: ERI kernel time per class */
+  double flops_class[HFX_N_CLASSES];      /* algorithmic FLOPs per class */
 } hfx_build_info;
 
 /* Device bytes hfx_plan would allocate for this system, excluding the

@@ -69,6 +69,8 @@ def lib():
         L.oracle_build_K.argtypes = [ctypes.c_void_p, ctypes.c_int64, i64p, ctypes.c_int, dp]
         L.oracle_quartets.restype = ctypes.c_int64
         L.oracle_quartets.argtypes = [ctypes.c_void_p, ctypes.c_int, ctypes.c_int64, i32p, dp]
+        L.oracle_eval_quartets.restype = ctypes.c_int64
+        L.oracle_eval_quartets.argtypes = [ctypes.c_void_p, ctypes.c_int64, i32p, dp]
         _lib = L
     return _lib
 
@@ -208,6 +210,38 @@ class Oracle:
         bnd = np.zeros(max(n, 1))
         lib().oracle_quartets(self.h, gR, n, _p(rows, ctypes.c_int32), _p(bnd))
         return rows[:n], bnd[:n]
+
+    def eval_quartets(self, rows: np.ndarray):
+        """Evaluate ordered quartets (rows of 13 ints) without screening;
+        returns (count, checksum).  For timing samples of a workload."""
+        rows = np.ascontiguousarray(rows, dtype=np.int32).reshape(-1, 13)
+        cs = ctypes.c_double(0.0)
+        n = lib().oracle_eval_quartets(self.h, len(rows), _p(rows, ctypes.c_int32), ctypes.byref(cs))
+        return int(n), float(cs.value)
+
+    def sample_quartets(self, n: int, seed: int = 0) -> np.ndarray:
+        """n ordered quartets (I^0 J^N | K^G L^H) drawn uniformly from the
+        plain loop of Eq. H-HFX: a K block (I, K, G), a bra pair of row I, a
+        ket pair of row K, kept when the density block (J, L, H-N) exists."""
+        rng = np.random.default_rng(seed)
+        b = self.blocks.astype(np.int64)
+        rows_of = {}
+        for i, r in enumerate(b[:, 0]):
+            rows_of.setdefault(int(r), []).append(i)
+        keys = self.block_key_index()
+        out = []
+        while len(out) < n:
+            kb = b[rng.integers(len(b))]
+            I, K, G = int(kb[0]), int(kb[1]), kb[2:5]
+            pb = b[rows_of[I][rng.integers(len(rows_of[I]))]]
+            qb = b[rows_of[K][rng.integers(len(rows_of[K]))]]
+            J, N = int(pb[1]), pb[2:5]
+            L, M = int(qb[1]), qb[2:5]
+            H = G + M
+            if (J, L) + tuple(int(v) for v in (H - N)) not in keys:
+                continue
+            out.append([I, J, *N, K, L, *M, *G])
+        return np.array(out, dtype=np.int32)
 
     def block_key_index(self):
         return {tuple(int(v) for v in b): i for i, b in enumerate(self.blocks)}

@@ -685,3 +685,44 @@ int64_t oracle_quartets(void *h, int gR, int64_t cap, int32_t *out_i, double *ou
   }
   return cnt;
 }
+
+/* Evaluate the given ordered quartets (rows of 13 ints as in
+ * oracle_quartets) one by one - contracted Cartesian integrals plus the K
+ * contraction with the D block - without screening.  Used to time the
+ * oracle on a sample of a workload.  Returns the number evaluated; *checksum
+ * receives the sum of the contributions (keeps the work observable). */
+int64_t oracle_eval_quartets(void *h, int64_t n, const int32_t *rows, double *checksum) {
+  osys *s = (osys *)h;
+  double total = 0.0;
+  int64_t done = 0;
+#pragma omp parallel for schedule(dynamic, 8) reduction(+ : total, done)
+  for (int64_t r = 0; r < n; ++r) {
+    const int32_t *o = rows + 13 * r;
+    int I = o[0], J = o[1], N[3] = {o[2], o[3], o[4]};
+    int K = o[5], L = o[6], M[3] = {o[7], o[8], o[9]};
+    int G[3] = {o[10], o[11], o[12]};
+    int H[3] = {G[0] + M[0], G[1] + M[1], G[2] + M[2]};
+    int z[3] = {0, 0, 0};
+    oshell A, B, C, D;
+    make_shell(s, I, z, &A);
+    make_shell(s, J, N, &B);
+    make_shell(s, K, G, &C);
+    make_shell(s, L, H, &D);
+    double eri[1296];
+    oracle_eri_quartet(&A, &B, &C, &D, s->op, s->omega, eri);
+    int64_t db = find_block(s, J, L, H[0] - N[0], H[1] - N[1], H[2] - N[2]);
+    int na = ncart(A.l), nb = ncart(B.l), nc = ncart(C.l), nd = ncart(D.l);
+    double acc = 0.0;
+    if (db >= 0) {
+      const double *dc = s->Dc + s->blk_coff[db];
+      for (int a = 0; a < na; ++a)
+        for (int c = 0; c < nc; ++c)
+          for (int b = 0; b < nb; ++b)
+            for (int d = 0; d < nd; ++d) acc += eri[((a * nb + b) * nc + c) * nd + d] * dc[b * nd + d];
+    }
+    total += acc;
+    done += 1;
+  }
+  if (checksum) *checksum = total;
+  return done;
+}

@@ -34,7 +34,8 @@ def _stale(src: str, obj: str) -> bool:
         return True
     t = os.path.getmtime(obj)
     deps = [os.path.join(CSRC, src)] + [os.path.join(CSRC, h) for h in os.listdir(CSRC) if h.endswith(".hpp")]
-    deps.append(os.path.join(ROOT, "include", "hfx.h"))
+    if src.endswith(".cpp"):
+        deps.append(os.path.join(ROOT, "include", "hfx.h"))
     return any(os.path.getmtime(d) > t for d in deps)
 
 

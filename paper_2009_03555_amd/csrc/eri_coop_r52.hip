@@ -1,0 +1,3 @@
+// Wave-cooperative ERI + digest kernel of bra pair class 5, ket pair class 2.
+#include "eri_coop.hpp"
+HFX_COOP_UNIT(5, 2)

@@ -3,6 +3,7 @@
 // device upload, and the build sequence (density -> screen -> ERI -> K).
 #include <algorithm>
 #include <cmath>
+#include <cstdlib>
 #include <cstring>
 #include <mutex>
 #include <string>
@@ -10,6 +11,7 @@
 #include <vector>
 
 #include "../../include/hfx.h"
+#include "coop.hpp"
 #include "launchers.hpp"
 
 using namespace hfx;
@@ -158,6 +160,9 @@ struct hfx_plan_s {
   uint64_t *d_list = nullptr;
   int64_t list_cap = 0;
   bool schwarz_done = false;
+  // ---- cooperative (LDS) kernels for high angular-momentum classes
+  bool use_coop[kNQuartetClass] = {false};
+  CoopDev coop[kNQuartetClass] = {};
   // ---- last build
   int64_t region_q[kNQuartetClass + 1] = {0};
   int64_t nq_total = 0;
@@ -521,6 +526,47 @@ hfx_status upload_plan(hfx_plan_s &P) {
                      P.scan_tmp_bytes, P.stream));
   HIPCHK(P.mem.alloc((char **)&P.d_scan_tmp, P.scan_tmp_bytes));
 
+  // cooperative kernels: classes whose register-resident recursion would
+  // spill (d shells with total angular momentum >= 5)
+  const char *mask_env = std::getenv("HFX_COOP_MASK");
+  for (int cb = 0; cb < kNPairClass; ++cb)
+    for (int ck = 0; ck <= cb; ++ck) {
+      const int r = region_of(cb, ck);
+      const int Lt = class_la(cb) + class_lb(cb) + class_la(ck) + class_lb(ck);
+      bool use = (cb >= 4 && Lt >= 6);
+      if (mask_env) use = ((std::strtoull(mask_env, nullptr, 0) >> r) & 1ull) != 0;
+      if (!use || !coop_available(cb, ck)) continue;
+      CoopHost h;
+      coop_build(cb, ck, 64 / coop_parallel(cb, ck), h);
+      if (h.n_vrr_levels != Lt) return fail(HFX_ERR_DEVICE, "internal: cooperative level structure");
+      for (int lv = 0; lv < h.n_vrr_levels; ++lv)
+        if (h.levels[lv].y != coop_level_count(cb, ck, lv) || h.levels[lv].x != (lv ? h.levels[lv - 1].x + h.levels[lv - 1].y : 0))
+          return fail(HFX_ERR_DEVICE, "internal: cooperative op list does not match the kernel shape");
+      uint4 *d_ops = nullptr, *d_vops = nullptr;
+      int4 *d_lv = nullptr;
+      uint16_t *d_acc = nullptr;
+      HIPCHK(upload(P, &d_ops, h.ops));
+      HIPCHK(upload(P, &d_vops, h.vops));
+      HIPCHK(upload(P, &d_lv, h.levels));
+      HIPCHK(upload(P, &d_acc, h.acc_off));
+      CoopDev &c = P.coop[r];
+      c.ops = d_ops;
+      c.vops = d_vops;
+      c.levels = d_lv;
+      c.acc_off = d_acc;
+      c.n_vrr_levels = h.n_vrr_levels;
+      c.n_hrr_levels = h.n_hrr_levels;
+      c.nacc = h.nacc;
+      c.nout = h.nout;
+      c.nw = h.nw;
+      c.out_base = h.out_base;
+      c.na = ncart(h.la);
+      c.nb = ncart(h.lb);
+      c.nc = ncart(h.lc);
+      c.nd = ncart(h.ld);
+      P.use_coop[r] = true;
+    }
+
   DevSys &s = P.ds;
   s.sh_xyz = P.d_sh_xyz;
   s.sh_l = P.d_sh_l;
@@ -740,11 +786,25 @@ static hfx_status build_one(hfx_plan_s &P, const double *d_dev, double *k_dev, u
   // ERI + digest
   launch_zero(P.d_K4, P.nnz_c, P.stream);
   launch_zero_u64(P.d_nprim, kNQuartetClass, P.stream);
+  hipEvent_t evc[kNQuartetClass + 1];
+  if (timing)
+    for (auto &e : evc) HIPCHK(hipEventCreate(&e));
   for (int cb = kNPairClass - 1; cb >= 0; --cb)
     for (int ck = cb; ck >= 0; --ck) {
       const int r = region_of(cb, ck);
       const int64_t n = P.region_q[r + 1] - P.region_q[r];
-      if (n > 0) launch_eri(cb, ck, P.op, P.ds, P.d_list + P.region_q[r], n, P.d_Dc, P.d_K4, P.d_nprim + r, P.stream);
+      if (timing) HIPCHK(hipEventRecord(evc[r], P.stream));
+      if (n > 0) {
+        if (P.use_coop[r]) {
+          const int Lt = class_la(cb) + class_lb(cb) + class_la(ck) + class_lb(ck);
+          (void)Lt;
+          launch_eri_coop(cb, ck, P.op, P.ds, P.coop[r], P.d_list + P.region_q[r], n, P.d_Dc, P.d_K4,
+                          P.d_nprim + r, P.stream);
+        } else {
+          launch_eri(cb, ck, P.op, P.ds, P.d_list + P.region_q[r], n, P.d_Dc, P.d_K4, P.d_nprim + r, P.stream);
+        }
+      }
+      if (timing && r == 0) HIPCHK(hipEventRecord(evc[kNQuartetClass], P.stream));
     }
   if (timing) HIPCHK(hipEventRecord(ev[3], P.stream));
   launch_finalize(P.ds, (int64_t)P.blocks.size(), P.d_blk_IJ, P.d_blk_off, P.d_partner, P.sph, P.d_K4, k_dev, P.stream);
@@ -769,9 +829,22 @@ static hfx_status build_one(hfx_plan_s &P, const double *d_dev, double *k_dev, u
         info->n_prim_quartets += (int64_t)np[r];
         double fp, fq;
         class_flops(class_la(cb), class_lb(cb), class_la(ck), class_lb(ck), P.op, fp, fq);
-        fl += fp * (double)np[r] + fq * (double)info->n_quartets_class[r];
+        info->flops_class[r] = fp * (double)np[r] + fq * (double)info->n_quartets_class[r];
+        fl += info->flops_class[r];
       }
     info->flops = fl;
+    if (timing) {
+      // regions were launched in descending order: class r ends where the next one starts
+      int order[kNQuartetClass], k = 0;
+      for (int cb = kNPairClass - 1; cb >= 0; --cb)
+        for (int ck = cb; ck >= 0; --ck) order[k++] = region_of(cb, ck);
+      for (int i = 0; i < kNQuartetClass; ++i) {
+        hipEvent_t end = (i + 1 < kNQuartetClass) ? evc[order[i + 1]] : evc[kNQuartetClass];
+        float ms;
+        HIPCHK(hipEventElapsedTime(&ms, evc[order[i]], end));
+        info->ms_class[order[i]] = ms;
+      }
+    }
     if (timing) {
       float ms;
       HIPCHK(hipEventElapsedTime(&ms, ev[0], ev[1]));
@@ -786,8 +859,10 @@ static hfx_status build_one(hfx_plan_s &P, const double *d_dev, double *k_dev, u
       info->ms_total = ms;
     }
   }
-  if (timing)
+  if (timing) {
     for (auto &e : ev) (void)hipEventDestroy(e);
+    for (auto &e : evc) (void)hipEventDestroy(e);
+  }
   return HFX_OK;
 }
 

@@ -3,6 +3,7 @@
 // times P_scr, 8-fold unique enumeration), K finalisation, fills.
 #include <hipcub/hipcub.hpp>
 
+#include "coop.hpp"
 #include "launchers.hpp"
 
 namespace hfx {
@@ -19,6 +20,38 @@ void launch_eri(int cb, int ck, int op, const DevSys &s, const uint64_t *list, i
       launch_eri_r53, launch_eri_r54, launch_eri_r55};
   if (cb < 0 || cb >= kNPairClass || ck < 0 || ck > cb) return;
   table[region_of(cb, ck)](op, s, list, nq, Dc, K4, nprim, st);
+}
+
+void launch_eri_coop_r42(int op, const DevSys &s, const CoopDev &cd, const uint64_t *l, int64_t n, const double *D,
+                           double *K, unsigned long long *c, hipStream_t st);
+void launch_eri_coop_r43(int op, const DevSys &s, const CoopDev &cd, const uint64_t *l, int64_t n, const double *D,
+                           double *K, unsigned long long *c, hipStream_t st);
+void launch_eri_coop_r44(int op, const DevSys &s, const CoopDev &cd, const uint64_t *l, int64_t n, const double *D,
+                           double *K, unsigned long long *c, hipStream_t st);
+void launch_eri_coop_r51(int op, const DevSys &s, const CoopDev &cd, const uint64_t *l, int64_t n, const double *D,
+                           double *K, unsigned long long *c, hipStream_t st);
+void launch_eri_coop_r52(int op, const DevSys &s, const CoopDev &cd, const uint64_t *l, int64_t n, const double *D,
+                           double *K, unsigned long long *c, hipStream_t st);
+void launch_eri_coop_r53(int op, const DevSys &s, const CoopDev &cd, const uint64_t *l, int64_t n, const double *D,
+                           double *K, unsigned long long *c, hipStream_t st);
+void launch_eri_coop_r54(int op, const DevSys &s, const CoopDev &cd, const uint64_t *l, int64_t n, const double *D,
+                           double *K, unsigned long long *c, hipStream_t st);
+void launch_eri_coop_r55(int op, const DevSys &s, const CoopDev &cd, const uint64_t *l, int64_t n, const double *D,
+                           double *K, unsigned long long *c, hipStream_t st);
+
+void launch_eri_coop(int cb, int ck, int op, const DevSys &s, const CoopDev &cd, const uint64_t *list, int64_t nq,
+                     const double *Dc, double *K4, unsigned long long *nprim, hipStream_t st) {
+  switch (cb * 10 + ck) {
+    case 42: launch_eri_coop_r42(op, s, cd, list, nq, Dc, K4, nprim, st); break;
+    case 43: launch_eri_coop_r43(op, s, cd, list, nq, Dc, K4, nprim, st); break;
+    case 44: launch_eri_coop_r44(op, s, cd, list, nq, Dc, K4, nprim, st); break;
+    case 51: launch_eri_coop_r51(op, s, cd, list, nq, Dc, K4, nprim, st); break;
+    case 52: launch_eri_coop_r52(op, s, cd, list, nq, Dc, K4, nprim, st); break;
+    case 53: launch_eri_coop_r53(op, s, cd, list, nq, Dc, K4, nprim, st); break;
+    case 54: launch_eri_coop_r54(op, s, cd, list, nq, Dc, K4, nprim, st); break;
+    case 55: launch_eri_coop_r55(op, s, cd, list, nq, Dc, K4, nprim, st); break;
+    default: break;
+  }
 }
 
 void launch_schwarz(int cb, int op, const DevSys &s, int p0, int p1, hipStream_t st) {

@@ -56,11 +56,14 @@ class hfx_build_info(ctypes.Structure):
                 ("n_prim_quartets", ctypes.c_int64), ("n_fp32_quartets", ctypes.c_int64),
                 ("flops", ctypes.c_double), ("ms_density", ctypes.c_double),
                 ("ms_screen", ctypes.c_double), ("ms_eri", ctypes.c_double),
-                ("ms_finalize", ctypes.c_double), ("ms_total", ctypes.c_double)]
+                ("ms_finalize", ctypes.c_double), ("ms_total", ctypes.c_double),
+                ("ms_class", ctypes.c_double * N_CLASSES), ("flops_class", ctypes.c_double * N_CLASSES)]
 
     def as_dict(self):
-        d = {k: getattr(self, k) for k, _ in self._fields_ if k != "n_quartets_class"}
-        d["n_quartets_class"] = list(self.n_quartets_class)
+        d = {}
+        for k, _ in self._fields_:
+            v = getattr(self, k)
+            d[k] = list(v) if k in ("n_quartets_class", "ms_class", "flops_class") else v
         return d
 
 
