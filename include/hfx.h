@@ -68,6 +68,7 @@ typedef enum { HFX_FP64 = 0, HFX_MIXED = 1 } hfx_precision;
 /* flags for hfx_build_K */
 #define HFX_SYNC 1u        /* synchronise the stream before returning */
 #define HFX_TIMING 2u      /* record per-phase times into info (implies SYNC) */
+#define HFX_GRAPH 4u       /* replay the build as a captured HIP graph (see below) */
 
 typedef struct hfx_plan_s *hfx_plan_t;
 
@@ -133,23 +134,40 @@ hfx_status hfx_pattern(hfx_plan_t plan, int64_t *n_blocks, int64_t *nnz, const h
  * n_blocks doubles to receive them.  *n_pairs: number of unique pairs. */
 hfx_status hfx_schwarz(hfx_plan_t plan, double *q_host, int64_t *n_pairs);
 
-/* One exchange build: d_dev, k_dev are device arrays of nnz doubles in the
- * pattern layout (caller-owned).  K is overwritten.  Runs hfx_schwarz first
- * if it has not run.  Asynchronous on the plan's stream unless HFX_SYNC. */
+/* One exchange build (Eq. H-HFX with the screening of Eq. screen):
+ * d_dev, k_dev are device arrays of nnz doubles in the pattern layout
+ * (caller-owned).  K is overwritten.  Runs hfx_schwarz first if it has not
+ * run.  Asynchronous on the plan's stream unless HFX_SYNC, HFX_TIMING or
+ * info is given.
+ *
+ * HFX_GRAPH: after one eager build has sized the quartet lists, the whole
+ * build (density transform, screening, every ERI class, finalisation) is
+ * captured once per (d_dev, k_dev) pair into a HIP graph with list capacity
+ * 1.25x the last size, and replayed.  A replay whose screened list outgrows
+ * that capacity is detected on the device and redone eagerly (the next call
+ * captures again).  Graph builds synchronise the stream before returning.
+ * HFX_TIMING takes precedence over HFX_GRAPH. */
 hfx_status hfx_build_K(hfx_plan_t plan, const double *d_dev, double *k_dev, uint32_t flags,
                        hfx_build_info *info);
 
-/* Several plans (each with its own D and K) in one fused launch sequence on
- * the first plan's stream.  Results equal n separate hfx_build_K calls. */
+/* Several plans (each with its own D and K, all on one device) in fused
+ * launches: one screening pass and one ERI launch per class cover every
+ * plan of one operator; plans of the two operators form two such groups.
+ * Runs on the stream of the first plan of each group.  Results equal n
+ * separate hfx_build_K calls.  The fused state is cached per plan list (and
+ * dropped when one of its plans is destroyed); flags as for hfx_build_K;
+ * info sums over all plans.  A plan may appear at most once. */
 hfx_status hfx_build_K_multi(int32_t n, const hfx_plan_t *plans, const double *const *d_dev,
                              double *const *k_dev, uint32_t flags, hfx_build_info *info);
 
-/* Host copies of the last build's screening data, for verification:
+/* Host copies of the last hfx_build_K's screening data, for verification:
  * what = 0: P_max per pattern block (n doubles, n = n_blocks);
  * what = 1: quartet list as uint64 (bra pair | ket pair << 24 | image << 48),
  *           n = number of quartets;
  * what = 2: unique pair table as int32 [n][6] (A, B, n1, n2, n3, class);
- * what = 3: Schwarz factor per unique pair (n doubles).
+ * what = 3: Schwarz factor per unique pair (n doubles);
+ * what = 5: mixed precision: the FP32-path quartet list (uint64, as what = 1;
+ *           what = 1 then holds the FP64-path quartets).
  * With host == NULL only *n is set. */
 hfx_status hfx_export(hfx_plan_t plan, int32_t what, void *host, int64_t *n);
 

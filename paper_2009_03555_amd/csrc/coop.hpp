@@ -66,7 +66,11 @@ __host__ __device__ constexpr bool coop_available(int cb, int ck) {
 // level sizes of the VRR op list (must equal the kernel's compile-time shape)
 int coop_level_count(int cb, int ck, int lv);
 
-void launch_eri_coop(int cb, int ck, int op, const DevSys &s, const CoopDev &cd, const uint64_t *list, int64_t nq,
-                     const double *Dc, double *K4, unsigned long long *nprim, hipStream_t st);
+// Schwarz factors of pair class cb (4 or 5) through the cooperative kernel of
+// class (cb|cb); cd must be that class's tables
+void launch_schwarz_coop(int cb, int op, const DevSys *sys1, const CoopDev &cd, int p0, int p1, hipStream_t st);
+
+struct SegLaunch;
+void launch_eri_coop(int cb, int ck, int op, const CoopDev &cd, const SegLaunch &L);
 
 }  // namespace hfx

@@ -58,11 +58,15 @@ __device__ __forceinline__ double lds(const char *base, uint32_t byte_off) {
 constexpr int kCoopBatch = 16;
 constexpr int kCoopStage = 26;  // doubles staged per primitive quartet: ladder (<= 9) + 17 factors
 
-template <int CB, int CK, int OP, int P>
-__global__ __launch_bounds__(64) void eri_coop_kernel(DevSys s, CoopDev cd, const uint64_t *__restrict__ list,
-                                                      int64_t nq, const double *__restrict__ Dc,
-                                                      double *__restrict__ K4,
-                                                      unsigned long long *__restrict__ nprim) {
+// MODE 0: ERI + digest over a quartet list.  MODE 1: Schwarz factors of the
+// pairs p0 .. p0+nq-1 of class CB (= CK): (ab|ab) over all primitive pairs,
+// Q_p = sqrt(max |(ab|ab)|) written to s.pr_Q.
+template <int CB, int CK, int OP, int P, int MODE>
+__global__ __launch_bounds__(64) void eri_coop_kernel(const DevSys *__restrict__ sys, int nsys,
+                                                      const int64_t *__restrict__ seg, CoopDev cd,
+                                                      const uint64_t *__restrict__ list,
+                                                      unsigned long long *__restrict__ nprim, int p0,
+                                                      int64_t npairs) {
   constexpr int GL = 64 / P;
   using SH = CoopShape<CB, CK, GL>;
   using SH64 = CoopShape<CB, CK, 64>;
@@ -93,14 +97,26 @@ __global__ __launch_bounds__(64) void eri_coop_kernel(DevSys s, CoopDev cd, cons
     accoff[k] = tt < SH64::NACC ? 8u * cd.acc_off[tt] : 0u;
   }
   unsigned long long prims = 0;
-  for (int64_t qi = blockIdx.x; qi < nq; qi += gridDim.x) {
-    const uint64_t q = list[qi];
-    const int bra = (int)(q & 0xFFFFFFull);
-    const int ket = (int)((q >> 24) & 0xFFFFFFull);
-    int g1, g2, g3;
-    unpack_img5((uint32_t)(q >> 48), g1, g2, g3);
+  const int64_t q0 = MODE == 0 ? seg[0] : 0, q1 = MODE == 0 ? seg[nsys] : npairs;
+  for (int64_t qi = q0 + blockIdx.x; qi < q1; qi += gridDim.x) {
+    const DevSys &s = sys[(MODE == 0 && nsys > 1) ? plan_of(seg, nsys, qi) : 0];
+    const double *__restrict__ Dc = s.Dc;
+    double *__restrict__ K4 = s.K4;
+    int bra, ket, g1 = 0, g2 = 0, g3 = 0;
+    if constexpr (MODE == 0) {
+      const uint64_t q = list[qi];
+      bra = (int)(q & 0xFFFFFFull);
+      ket = (int)((q >> 24) & 0xFFFFFFull);
+      unpack_img5((uint32_t)(q >> 48), g1, g2, g3);
+    } else {
+      bra = ket = p0 + (int)qi;
+    }
     const int4 bi = s.pr_info[bra], ki = s.pr_info[ket];
-    const int2 bpp = s.pr_pp[bra], kpp = s.pr_pp[ket];
+    int2 bpp = s.pr_pp[bra], kpp = s.pr_pp[ket];
+    if constexpr (MODE == 1) {
+      bpp.y = s.pr_npp[bra];
+      kpp.y = bpp.y;
+    }
     double gx = 0.0, gy = 0.0, gz = 0.0;
     if (s.periodic) {
       gx = g1 * s.lat[0] + g2 * s.lat[3] + g3 * s.lat[6];
@@ -221,9 +237,21 @@ __global__ __launch_bounds__(64) void eri_coop_kernel(DevSys s, CoopDev cd, cons
       }
       __syncthreads();
     }
-    // digest: lanes over the output elements of each contribution
     const double *v = W + cd.out_base;
     constexpr int NA = ncart(SH::LA), NB = ncart(SH::LB), NC = ncart(SH::LC), ND = ncart(SH::LD);
+    if constexpr (MODE == 1) {
+      double m = 0.0;
+      for (int o = lane; o < NA * NB; o += 64) {
+        const int a = o / NB, b = o - a * NB;
+        m = fmax(m, fabs(v[((a * NB + b) * NA + a) * NB + b]));
+      }
+#pragma unroll
+      for (int d = 32; d >= 1; d >>= 1) m = fmax(m, __shfl_xor(m, d));
+      if (lane == 0) s.pr_Q[bra] = sqrt(m);
+      __syncthreads();
+      continue;
+    }
+    // digest: lanes over the output elements of each contribution
     int nB1, nB2, nB3, nD1, nD2, nD3;
     unpack_img8(bi.z, nB1, nB2, nB3);
     unpack_img8(ki.z, nD1, nD2, nD3);
@@ -278,31 +306,53 @@ __global__ __launch_bounds__(64) void eri_coop_kernel(DevSys s, CoopDev cd, cons
     }
     __syncthreads();
   }
-  if (lane == 0 && prims) atomicAdd(nprim, prims);
+  if constexpr (MODE == 0)
+    if (lane == 0 && prims) atomicAdd(nprim, prims);
 }
 
 // primitive quartets evaluated side by side per wave, by class size
 template <int CB, int CK, int OP>
-void launch_coop_t(const DevSys &s, const CoopDev &cd, const uint64_t *list, int64_t nq, const double *Dc,
-                   double *K4, unsigned long long *nprim, hipStream_t st) {
-  if (nq <= 0) return;
+void launch_coop_t(const CoopDev &cd, const SegLaunch &L) {
+  if (L.nq_hint == 0) return;
   constexpr int P = coop_parallel(CB, CK);
-  const int64_t blocks = nq < 256 * 32 ? nq : 256 * 32;
+  const int64_t blocks = (L.nq_hint > 0 && L.nq_hint < 256 * 32) ? L.nq_hint : 256 * 32;
   const size_t lds = ((size_t)P * (cd.nw + 1) + (size_t)kCoopBatch * kCoopStage) * sizeof(double);
-  hipLaunchKernelGGL((eri_coop_kernel<CB, CK, OP, P>), dim3((unsigned)blocks), dim3(64), lds, st, s, cd, list, nq,
-                     Dc, K4, nprim);
+  hipLaunchKernelGGL((eri_coop_kernel<CB, CK, OP, P, 0>), dim3((unsigned)blocks), dim3(64), lds, L.stream, L.sys,
+                     L.nsys, L.seg, cd, L.list, L.nprim, 0, (int64_t)0);
+}
+
+// sys1: device descriptor of the one plan whose pairs p0 .. p1-1 are processed
+template <int CB, int OP>
+void launch_coop_schwarz_t(const DevSys *sys1, const CoopDev &cd, int p0, int p1, hipStream_t st) {
+  if (p1 <= p0) return;
+  constexpr int P = coop_parallel(CB, CB);
+  const int64_t n = p1 - p0;
+  const int64_t blocks = n < 256 * 32 ? n : 256 * 32;
+  const size_t lds = ((size_t)P * (cd.nw + 1) + (size_t)kCoopBatch * kCoopStage) * sizeof(double);
+  hipLaunchKernelGGL((eri_coop_kernel<CB, CB, OP, P, 1>), dim3((unsigned)blocks), dim3(64), lds, st, sys1, 1,
+                     (const int64_t *)nullptr, cd, (const uint64_t *)nullptr, (unsigned long long *)nullptr, p0,
+                     n);
 }
 
 }  // namespace hfx
 
-#define HFX_COOP_UNIT(CB, CK)                                                                        \
+#define HFX_COOP_SCHWARZ_UNIT(CB)                                                                    \
   namespace hfx {                                                                                    \
-  void launch_eri_coop_r##CB##CK(int op, const DevSys &s, const CoopDev &cd, const uint64_t *l,      \
-                                 int64_t n, const double *D, double *K, unsigned long long *c,        \
+  void launch_schwarz_coop_c##CB(int op, const DevSys *sys1, const CoopDev &cd, int p0, int p1,     \
                                  hipStream_t st) {                                                   \
     if (op == 0)                                                                                     \
-      launch_coop_t<CB, CK, 0>(s, cd, l, n, D, K, c, st);                                            \
+      launch_coop_schwarz_t<CB, 0>(sys1, cd, p0, p1, st);                                            \
     else                                                                                             \
-      launch_coop_t<CB, CK, 1>(s, cd, l, n, D, K, c, st);                                            \
+      launch_coop_schwarz_t<CB, 1>(sys1, cd, p0, p1, st);                                            \
+  }                                                                                                  \
+  }
+
+#define HFX_COOP_UNIT(CB, CK)                                                                        \
+  namespace hfx {                                                                                    \
+  void launch_eri_coop_r##CB##CK(int op, const CoopDev &cd, const SegLaunch &L) {                  \
+    if (op == 0)                                                                                     \
+      launch_coop_t<CB, CK, 0>(cd, L);                                                               \
+    else                                                                                             \
+      launch_coop_t<CB, CK, 1>(cd, L);                                                               \
   }                                                                                                  \
   }

@@ -1,0 +1,4 @@
+// ERI + digest kernels of bra pair class 4, ket pair class 3: FP32 recursion and
+// primitive sum (mixed precision), FP64 ladder, HRR and digest.
+#include "eri_kernels.hpp"
+HFX_ERI_F32_UNIT(4, 3)

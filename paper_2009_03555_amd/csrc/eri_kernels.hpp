@@ -94,16 +94,23 @@ __device__ __forceinline__ void digest(const DevSys &s, int bAC, int bAD, int bB
 }
 
 // --------------------------------------------------------- ERI + digest
-// One lane per unique quartet of the class segment (grid-stride loop).
-template <int CB, int CK, int OP>
-__global__ __launch_bounds__(256) void eri_digest_kernel(DevSys s, const uint64_t *__restrict__ list,
-                                                         int64_t nq, const double *__restrict__ Dc,
-                                                         double *__restrict__ K4,
+// One lane per unique quartet of the class segment (grid-stride loop).  The
+// segment [seg[0], seg[nsys]) of the fused list holds the class's quartets of
+// nsys plans (plan i: [seg[i], seg[i+1])); bounds are read on the device so
+// the launch does not depend on host-side counts.
+template <int CB, int CK, int OP, typename TV>
+__global__ __launch_bounds__(256) void eri_digest_kernel(const DevSys *__restrict__ sys, int nsys,
+                                                         const int64_t *__restrict__ seg,
+                                                         const uint64_t *__restrict__ list,
                                                          unsigned long long *__restrict__ nprim) {
   using C = Cls<class_la(CB), class_lb(CB), class_la(CK), class_lb(CK)>;
   const int64_t nthreads = (int64_t)gridDim.x * blockDim.x;
+  const int64_t q0 = seg[0], q1 = seg[nsys];
   unsigned long long prims = 0;
-  for (int64_t qi = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; qi < nq; qi += nthreads) {
+  for (int64_t qi = q0 + (int64_t)blockIdx.x * blockDim.x + threadIdx.x; qi < q1; qi += nthreads) {
+    const DevSys &s = sys[nsys > 1 ? plan_of(seg, nsys, qi) : 0];
+    const double *__restrict__ Dc = s.Dc;
+    double *__restrict__ K4 = s.K4;
     const uint64_t q = list[qi];
     const int bra = (int)(q & 0xFFFFFFull);
     const int ket = (int)((q >> 24) & 0xFFFFFFull);
@@ -117,12 +124,15 @@ __global__ __launch_bounds__(256) void eri_digest_kernel(DevSys s, const uint64_
       gy = g1 * s.lat[1] + g2 * s.lat[4] + g3 * s.lat[7];
       gz = g1 * s.lat[2] + g2 * s.lat[5] + g3 * s.lat[8];
     }
+    TV acct[C::NACC];
+#pragma unroll
+    for (int k = 0; k < C::NACC; ++k) acct[k] = (TV)0;
+    prim_sum<C, OP, TV>(s, s.pp + (int64_t)bpp.x * kPP, bpp.y, s.pp + (int64_t)kpp.x * kPP, kpp.y, gx, gy,
+                        gz, 0, 1, acct);
+    prims += (unsigned long long)bpp.y * kpp.y;
     double acc[C::NACC];
 #pragma unroll
-    for (int k = 0; k < C::NACC; ++k) acc[k] = 0.0;
-    prim_sum<C, OP>(s, s.pp + (int64_t)bpp.x * kPP, bpp.y, s.pp + (int64_t)kpp.x * kPP, kpp.y, gx, gy, gz,
-                    0, 1, acc);
-    prims += (unsigned long long)bpp.y * kpp.y;
+    for (int k = 0; k < C::NACC; ++k) acc[k] = (double)acct[k];
     const double *bg = s.pr_geom + (int64_t)bra * 8;
     const double *kg = s.pr_geom + (int64_t)ket * 8;
     double AB[3] = {bg[0], bg[1], bg[2]};
@@ -180,15 +190,16 @@ __global__ __launch_bounds__(128) void schwarz_kernel(DevSys s, int p0, int p1) 
 }
 
 // ------------------------------------------------------------ launchers
-template <int CB, int CK, int OP>
-void launch_eri_t(const DevSys &s, const uint64_t *list, int64_t nq, const double *Dc, double *K4,
-                  unsigned long long *nprim, hipStream_t st) {
-  if (nq <= 0) return;
+// nq_hint: quartets in the segment if known on the host (sizes the grid),
+// or -1 (graph capture: a fixed grid that drains any count)
+template <int CB, int CK, int OP, typename TV = double>
+void launch_eri_t(const SegLaunch &L) {
+  if (L.nq_hint == 0) return;
   const int threads = 256;
-  int64_t blocks = (nq + threads - 1) / threads;
+  int64_t blocks = L.nq_hint > 0 ? (L.nq_hint + threads - 1) / threads : 256 * 8;
   if (blocks > 256 * 64) blocks = 256 * 64;
-  hipLaunchKernelGGL((eri_digest_kernel<CB, CK, OP>), dim3((unsigned)blocks), dim3(threads), 0, st, s, list,
-                     nq, Dc, K4, nprim);
+  hipLaunchKernelGGL((eri_digest_kernel<CB, CK, OP, TV>), dim3((unsigned)blocks), dim3(threads), 0, L.stream,
+                     L.sys, L.nsys, L.seg, L.list, L.nprim);
 }
 
 template <int CB, int OP>
@@ -206,12 +217,22 @@ void launch_schwarz_t(const DevSys &s, int p0, int p1, hipStream_t st) {
 // the Schwarz kernels of pair class CB.
 #define HFX_ERI_UNIT(CB, CK)                                                                         \
   namespace hfx {                                                                                    \
-  void launch_eri_r##CB##CK(int op, const DevSys &s, const uint64_t *l, int64_t n, const double *D,  \
-                            double *K, unsigned long long *c, hipStream_t st) {                      \
+  void launch_eri_r##CB##CK(int op, const SegLaunch &L) {                                           \
     if (op == 0)                                                                                     \
-      launch_eri_t<CB, CK, 0>(s, l, n, D, K, c, st);                                                 \
+      launch_eri_t<CB, CK, 0>(L);                                                                    \
     else                                                                                             \
-      launch_eri_t<CB, CK, 1>(s, l, n, D, K, c, st);                                                 \
+      launch_eri_t<CB, CK, 1>(L);                                                                    \
+  }                                                                                                  \
+  }
+
+// FP32-recursion variant of the region (mixed precision)
+#define HFX_ERI_F32_UNIT(CB, CK)                                                                     \
+  namespace hfx {                                                                                    \
+  void launch_eri_f32_r##CB##CK(int op, const SegLaunch &L) {                                       \
+    if (op == 0)                                                                                     \
+      launch_eri_t<CB, CK, 0, float>(L);                                                             \
+    else                                                                                             \
+      launch_eri_t<CB, CK, 1, float>(L);                                                             \
   }                                                                                                  \
   }
 

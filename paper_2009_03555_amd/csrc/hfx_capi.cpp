@@ -125,9 +125,6 @@ struct hfx_plan_s {
   std::vector<int32_t> pr_npp;
   std::vector<double> pp;
   int32_t class_start[kNPairClass + 1] = {0};
-  // ---- screening items
-  std::vector<int2> items;
-  int64_t region_item[kNQuartetClass + 1] = {0};
   // ---- device
   hipStream_t stream = nullptr;
   DevMem mem;
@@ -149,23 +146,15 @@ struct hfx_plan_s {
   unsigned long long *d_pglob = nullptr;
   double *d_Dc = nullptr, *d_K4 = nullptr;
   double *d_boys = nullptr;
-  int2 *d_items = nullptr;
-  int32_t *d_counts = nullptr;
-  int64_t *d_offsets = nullptr;
-  void *d_scan_tmp = nullptr;
-  size_t scan_tmp_bytes = 0;
-  int32_t *d_class_start = nullptr;
-  int32_t *d_err = nullptr;
-  unsigned long long *d_nprim = nullptr;  // per region
-  uint64_t *d_list = nullptr;
-  int64_t list_cap = 0;
+  DevSys *d_sys1 = nullptr;  // device copy of ds (one-plan launches)
   bool schwarz_done = false;
   // ---- cooperative (LDS) kernels for high angular-momentum classes
   bool use_coop[kNQuartetClass] = {false};
   CoopDev coop[kNQuartetClass] = {};
-  // ---- last build
-  int64_t region_q[kNQuartetClass + 1] = {0};
-  int64_t nq_total = 0;
+  // ---- FP32-list kernel per class: 0 FP32 register kernel, 1 the FP64 kernel
+  int fp32_kernel[kNQuartetClass] = {0};
+  // ---- cached one-plan batch (hfx_build_K)
+  struct Batch *self_batch = nullptr;
 };
 
 namespace {
@@ -474,15 +463,6 @@ hfx_status build_host(hfx_plan_s &P, const hfx_system *s) {
   if (ppoff >= (int64_t)INT32_MAX) return fail(HFX_ERR_UNSUPPORTED, "too many primitive pairs");
   for (int c = 0; c < kNPairClass; ++c) P.class_start[c + 1] += P.class_start[c];
 
-  // ---- screening work items: (region, bra pair), regions (cb >= ck)
-  for (int cb = 0; cb < kNPairClass; ++cb)
-    for (int ck = 0; ck <= cb; ++ck) {
-      const int r = region_of(cb, ck);
-      P.region_item[r] = (int64_t)P.items.size();
-      if (P.class_start[ck + 1] == P.class_start[ck]) continue;
-      for (int p = P.class_start[cb]; p < P.class_start[cb + 1]; ++p) P.items.push_back(make_int2(r, p));
-    }
-  P.region_item[kNQuartetClass] = (int64_t)P.items.size();
   return HFX_OK;
 }
 
@@ -514,18 +494,6 @@ hfx_status upload_plan(hfx_plan_s &P) {
   HIPCHK(P.mem.alloc(&P.d_Dc, (size_t)P.nnz_c));
   HIPCHK(P.mem.alloc(&P.d_K4, (size_t)P.nnz_c));
   HIPCHK(upload(P, &P.d_boys, boys_table()));
-  HIPCHK(upload(P, &P.d_items, P.items));
-  HIPCHK(P.mem.alloc(&P.d_counts, P.items.size()));
-  HIPCHK(P.mem.alloc(&P.d_offsets, P.items.size() + 1));
-  std::vector<int32_t> cs(P.class_start, P.class_start + kNPairClass + 1);
-  HIPCHK(upload(P, &P.d_class_start, cs));
-  HIPCHK(P.mem.alloc(&P.d_err, 2));
-  HIPCHK(P.mem.alloc(&P.d_nprim, kNQuartetClass));
-  P.scan_tmp_bytes = 0;
-  HIPCHK(scan_counts(P.d_counts, P.d_offsets, (int64_t)std::max<size_t>(P.items.size(), 1), nullptr,
-                     P.scan_tmp_bytes, P.stream));
-  HIPCHK(P.mem.alloc((char **)&P.d_scan_tmp, P.scan_tmp_bytes));
-
   // cooperative kernels: classes whose register-resident recursion would
   // spill (d shells with total angular momentum >= 5)
   const char *mask_env = std::getenv("HFX_COOP_MASK");
@@ -535,6 +503,7 @@ hfx_status upload_plan(hfx_plan_s &P) {
       const int Lt = class_la(cb) + class_lb(cb) + class_la(ck) + class_lb(ck);
       bool use = (cb >= 4 && Lt >= 6);
       if (mask_env) use = ((std::strtoull(mask_env, nullptr, 0) >> r) & 1ull) != 0;
+      if (!register_available(cb, ck)) use = true;  // no one-lane kernel: always cooperative
       if (!use || !coop_available(cb, ck)) continue;
       CoopHost h;
       coop_build(cb, ck, 64 / coop_parallel(cb, ck), h);
@@ -565,6 +534,8 @@ hfx_status upload_plan(hfx_plan_s &P) {
       c.nc = ncart(h.lc);
       c.nd = ncart(h.ld);
       P.use_coop[r] = true;
+      // mixed precision: FP32 one-lane kernel where it exists, else the FP64 cooperative one
+      P.fp32_kernel[r] = register_available(cb, ck) ? 0 : 1;
     }
 
   DevSys &s = P.ds;
@@ -592,7 +563,13 @@ hfx_status upload_plan(hfx_plan_s &P) {
   s.op = P.op;
   s.omega2 = P.omega * P.omega;
   s.tau = P.tau;
+  s.fp32_cutoff = P.precision == HFX_MIXED ? P.fp32_cutoff : 0.0;
   s.boys = P.d_boys;
+  s.Dc = P.d_Dc;
+  s.K4 = P.d_K4;
+  for (int c = 0; c <= kNPairClass; ++c) s.class_start[c] = P.class_start[c];
+  HIPCHK(P.mem.alloc(&P.d_sys1, 1));
+  HIPCHK(hipMemcpyAsync(P.d_sys1, &P.ds, sizeof(DevSys), hipMemcpyHostToDevice, P.stream));
   HIPCHK(hipStreamSynchronize(P.stream));
   return HFX_OK;
 }
@@ -607,8 +584,13 @@ bool valid_plan(hfx_plan_t p) {
 }
 
 hfx_status run_schwarz(hfx_plan_s &P) {
-  for (int c = 0; c < kNPairClass; ++c)
-    launch_schwarz(c, P.op, P.ds, P.class_start[c], P.class_start[c + 1], P.stream);
+  for (int c = 0; c < kNPairClass; ++c) {
+    if (c >= 4)
+      launch_schwarz_coop(c, P.op, P.d_sys1, P.coop[region_of(c, c)], P.class_start[c], P.class_start[c + 1],
+                          P.stream);
+    else
+      launch_schwarz(c, P.op, P.ds, P.class_start[c], P.class_start[c + 1], P.stream);
+  }
   HIPCHK(hipGetLastError());
   P.schwarz_done = true;
   return HFX_OK;
@@ -692,7 +674,10 @@ hfx_status hfx_footprint(const hfx_system *sys, size_t *device_bytes, size_t *li
   b += P.blocks.size() * (sizeof(int2) + 8 + 8 + 4 + 1 + 8) + 16;
   b += (size_t)P.nnz_c * 16;
   b += (size_t)kBoysRows * kBoysCols * 8;
-  b += P.items.size() * (sizeof(int2) + 4 + 8) + 8;
+  // screening work: one item per (class region, bra pair)
+  int64_t nitems = 0;
+  for (int cb = 0; cb < kNPairClass; ++cb) nitems += (int64_t)(cb + 1) * (P.class_start[cb + 1] - P.class_start[cb]);
+  b += (size_t)nitems * (sizeof(int4) + 4 + 8) + 8 + sizeof(DevSys);
   *device_bytes = b;
   if (list_bytes_per_quartet) *list_bytes_per_quartet = sizeof(uint64_t);
   return HFX_OK;
@@ -744,143 +729,442 @@ hfx_status hfx_schwarz(hfx_plan_t plan, double *q_host, int64_t *n_pairs) {
   return HFX_OK;
 }
 
-static hfx_status build_one(hfx_plan_s &P, const double *d_dev, double *k_dev, uint32_t flags, hfx_build_info *info) {
-  if (!d_dev || !k_dev) return fail(HFX_ERR_INVALID, "D or K pointer is NULL");
-  if (!P.schwarz_done) {
-    hfx_status st = run_schwarz(P);
+}  // extern "C"
+
+// ===================================================================
+// Batches: one or more plans built by fused launches.  A batch owns the
+// screening work items of its plans (region, bra pair, plan), the class-
+// segment bounds on the device, the quartet lists and an optional HIP graph
+// of the whole build.
+// ===================================================================
+struct Batch {
+  std::vector<hfx_plan_s *> plans;
+  int op = 0;
+  bool mixed = false;
+  hipStream_t stream = nullptr;
+  DevMem mem;
+  DevSys *d_sys = nullptr;
+  int4 *d_items = nullptr;
+  int64_t nitems = 0;
+  int32_t *d_counts = nullptr;
+  int64_t *d_offsets = nullptr;
+  int64_t *d_scan_tmp = nullptr;  // block sums
+  std::vector<int64_t> seg_items;  // [kNQuartetClass][n + 1]
+  int64_t *d_seg_items = nullptr;
+  int64_t *d_seg64 = nullptr, *d_seg32 = nullptr;
+  std::vector<int64_t> h_seg64, h_seg32;
+  uint64_t *d_list = nullptr, *d_list32 = nullptr;
+  int64_t cap = 0, cap32 = 0;
+  int64_t nq64 = 0, nq32 = 0;
+  int32_t *d_err = nullptr;
+  unsigned long long *d_nprim = nullptr;
+  bool have_counts = false;  // an eager build has filled h_seg* / nq*
+  // graph of the build for fixed (D, K) pointers
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t gexec = nullptr;
+  hipStream_t cap_stream = nullptr;  // private stream the build is captured on
+  std::vector<const double *> g_d;
+  std::vector<double *> g_k;
+  ~Batch() { release(); }
+  void release() {
+    if (gexec) (void)hipGraphExecDestroy(gexec);
+    if (graph) (void)hipGraphDestroy(graph);
+    gexec = nullptr;
+    graph = nullptr;
+    if (cap_stream) (void)hipStreamDestroy(cap_stream);
+    cap_stream = nullptr;
+    if (d_list) (void)hipFree(d_list);
+    if (d_list32) (void)hipFree(d_list32);
+    d_list = d_list32 = nullptr;
+    mem.release();
+  }
+  int n() const { return (int)plans.size(); }
+};
+
+namespace {
+
+std::mutex g_batch_mu;
+std::vector<Batch *> g_batches;  // multi-plan batches (one-plan batches live in their plan)
+
+hfx_status batch_init(Batch &B, const std::vector<hfx_plan_s *> &plans) {
+  B.plans = plans;
+  B.op = plans[0]->op;
+  B.stream = plans[0]->stream;
+  B.mixed = false;
+  for (auto *P : plans) B.mixed |= P->precision == HFX_MIXED;
+  const int n = (int)plans.size();
+  std::vector<DevSys> sys(n);
+  for (int i = 0; i < n; ++i) sys[i] = plans[i]->ds;
+  // items ordered by (region, plan, bra pair): every class segment of the
+  // fused list is contiguous and holds plan 0's quartets, then plan 1's, ...
+  std::vector<int4> items;
+  B.seg_items.assign((size_t)kNQuartetClass * (n + 1), 0);
+  for (int cb = 0; cb < kNPairClass; ++cb)
+    for (int ck = 0; ck <= cb; ++ck) {
+      const int r = region_of(cb, ck);
+      for (int i = 0; i < n; ++i) {
+        B.seg_items[(size_t)r * (n + 1) + i] = (int64_t)items.size();
+        const hfx_plan_s &P = *plans[i];
+        if (P.class_start[ck + 1] == P.class_start[ck]) continue;
+        for (int p = P.class_start[cb]; p < P.class_start[cb + 1]; ++p) items.push_back(make_int4(r, p, i, 0));
+      }
+      B.seg_items[(size_t)r * (n + 1) + n] = (int64_t)items.size();
+    }
+  B.nitems = (int64_t)items.size();
+  HIPCHK(B.mem.alloc(&B.d_sys, (size_t)n));
+  HIPCHK(hipMemcpyAsync(B.d_sys, sys.data(), n * sizeof(DevSys), hipMemcpyHostToDevice, B.stream));
+  HIPCHK(B.mem.alloc(&B.d_items, items.size()));
+  if (!items.empty())
+    HIPCHK(hipMemcpyAsync(B.d_items, items.data(), items.size() * sizeof(int4), hipMemcpyHostToDevice, B.stream));
+  HIPCHK(B.mem.alloc(&B.d_counts, items.size()));
+  HIPCHK(B.mem.alloc(&B.d_offsets, items.size() + 1));
+  HIPCHK(B.mem.alloc(&B.d_scan_tmp, (items.size() + 1023) / 1024 + 2));
+  HIPCHK(B.mem.alloc(&B.d_seg_items, B.seg_items.size()));
+  HIPCHK(hipMemcpyAsync(B.d_seg_items, B.seg_items.data(), B.seg_items.size() * 8, hipMemcpyHostToDevice, B.stream));
+  HIPCHK(B.mem.alloc(&B.d_seg64, B.seg_items.size()));
+  HIPCHK(B.mem.alloc(&B.d_seg32, B.seg_items.size()));
+  HIPCHK(B.mem.alloc(&B.d_err, 2));
+  HIPCHK(B.mem.alloc(&B.d_nprim, kNQuartetClass));
+  B.h_seg64.assign(B.seg_items.size(), 0);
+  B.h_seg32.assign(B.seg_items.size(), 0);
+  HIPCHK(hipStreamSynchronize(B.stream));
+  return HFX_OK;
+}
+
+hfx_status ensure_cap(uint64_t **list, int64_t *cap, int64_t need) {
+  if (need <= *cap && *list) return HFX_OK;
+  if (*list) HIPCHK(hipFree(*list));
+  *list = nullptr;
+  *cap = 0;
+  const int64_t c = need + need / 4 + 4096;
+  hipError_t e = hipMalloc((void **)list, (size_t)c * sizeof(uint64_t));
+  if (e != hipSuccess) return fail(HFX_ERR_OOM, "quartet list allocation failed");
+  *cap = c;
+  return HFX_OK;
+}
+
+void drop_graph(Batch &B) {
+  if (B.gexec) (void)hipGraphExecDestroy(B.gexec);
+  if (B.graph) (void)hipGraphDestroy(B.graph);
+  B.gexec = nullptr;
+  B.graph = nullptr;
+  B.g_d.clear();
+  B.g_k.clear();
+}
+
+// One screening pass (count, scan, bounds; eager: host read + allocation;
+// fill).  graph: no host interaction, the list must already have capacity.
+hfx_status screen_pass(Batch &B, int mode, bool graph, uint64_t **list, int64_t *cap, int64_t *d_seg,
+                       std::vector<int64_t> &h_seg, int64_t *total) {
+  launch_screen(B.d_sys, B.d_items, B.nitems, B.d_counts, B.d_offsets, nullptr, 0, B.d_err, false, mode, B.stream);
+  HIPCHK(scan_counts(B.d_counts, B.d_offsets, B.nitems, B.d_scan_tmp, B.stream));
+  launch_gather_bounds(B.d_offsets, B.d_seg_items, d_seg, (int)B.seg_items.size(), graph ? *cap : INT64_MAX,
+                       B.stream);
+  if (!graph) {
+    HIPCHK(hipMemcpyAsync(h_seg.data(), d_seg, h_seg.size() * 8, hipMemcpyDeviceToHost, B.stream));
+    HIPCHK(hipStreamSynchronize(B.stream));
+    *total = h_seg.empty() ? 0 : h_seg.back();
+    const uint64_t *before = *list;
+    hfx_status st = ensure_cap(list, cap, *total);
     if (st != HFX_OK) return st;
+    if (*list != before) drop_graph(B);  // a captured graph holds the old list
   }
-  const bool timing = (flags & HFX_TIMING) != 0;
-  hipEvent_t ev[5];
-  if (timing)
-    for (auto &e : ev) HIPCHK(hipEventCreate(&e));
-  if (timing) HIPCHK(hipEventRecord(ev[0], P.stream));
-  // density -> Cartesian blocks, P_max
-  launch_zero_u64(P.d_pglob, 1, P.stream);
-  launch_density(P.ds, (int64_t)P.blocks.size(), P.d_blk_IJ, P.d_blk_off, P.d_partner, P.d_canon, P.sph, d_dev, P.d_Dc,
-                 P.stream);
-  if (timing) HIPCHK(hipEventRecord(ev[1], P.stream));
-  // screen: count, scan, fill
-  const int64_t nitems = (int64_t)P.items.size();
-  launch_zero_u64((unsigned long long *)P.d_err, 1, P.stream);
-  launch_screen(P.ds, P.d_items, nitems, P.d_class_start, P.d_counts, P.d_offsets, nullptr, P.d_err, false, P.stream);
-  std::vector<int64_t> offs(nitems + 1, 0);
-  if (nitems > 0) {
-    HIPCHK(scan_counts(P.d_counts, P.d_offsets, nitems, P.d_scan_tmp, P.scan_tmp_bytes, P.stream));
-    HIPCHK(hipMemcpyAsync(offs.data(), P.d_offsets, (nitems + 1) * 8, hipMemcpyDeviceToHost, P.stream));
+  launch_screen(B.d_sys, B.d_items, B.nitems, B.d_counts, B.d_offsets, *list, *cap, B.d_err, true, mode, B.stream);
+  return HFX_OK;
+}
+
+// Enqueue the whole build of a batch on its stream.  graph = true: nothing
+// here waits for the device (the sequence is being captured).
+hfx_status enqueue_build(Batch &B, const double *const *d_dev, double *const *k_dev, bool graph, hipEvent_t *ev,
+                         hipEvent_t *evc) {
+  const int n = B.n();
+  hfx_plan_s &P0 = *B.plans[0];
+  if (ev) HIPCHK(hipEventRecord(ev[0], B.stream));
+  for (int i = 0; i < n; ++i) {
+    hfx_plan_s &P = *B.plans[i];
+    launch_zero_u64(P.d_pglob, 1, B.stream);
+    launch_density(P.ds, (int64_t)P.blocks.size(), P.d_blk_IJ, P.d_blk_off, P.d_partner, P.d_canon, P.sph, d_dev[i],
+                   P.d_Dc, B.stream);
+    launch_zero(P.d_K4, P.nnz_c, B.stream);
   }
-  HIPCHK(hipStreamSynchronize(P.stream));
-  for (int r = 0; r <= kNQuartetClass; ++r) P.region_q[r] = offs[P.region_item[r]];
-  P.nq_total = offs[nitems];
-  if (P.nq_total > P.list_cap) {
-    if (P.d_list) HIPCHK(hipFree(P.d_list));
-    P.d_list = nullptr;
-    P.list_cap = 0;
-    int64_t cap = P.nq_total + P.nq_total / 8 + 1024;
-    hipError_t e = hipMalloc((void **)&P.d_list, (size_t)cap * sizeof(uint64_t));
-    if (e != hipSuccess) return fail(HFX_ERR_OOM, "quartet list allocation failed");
-    P.list_cap = cap;
+  if (ev) HIPCHK(hipEventRecord(ev[1], B.stream));
+  launch_zero_i32(B.d_err, 2, B.stream);
+  launch_zero_u64(B.d_nprim, kNQuartetClass, B.stream);
+  hfx_status st = screen_pass(B, B.mixed ? 1 : 0, graph, &B.d_list, &B.cap, B.d_seg64, B.h_seg64, &B.nq64);
+  if (st != HFX_OK) return st;
+  if (B.mixed) {
+    st = screen_pass(B, 2, graph, &B.d_list32, &B.cap32, B.d_seg32, B.h_seg32, &B.nq32);
+    if (st != HFX_OK) return st;
+  } else if (!graph) {
+    B.nq32 = 0;
+    std::fill(B.h_seg32.begin(), B.h_seg32.end(), 0);
   }
-  launch_screen(P.ds, P.d_items, nitems, P.d_class_start, P.d_counts, P.d_offsets, P.d_list, P.d_err, true, P.stream);
-  if (timing) HIPCHK(hipEventRecord(ev[2], P.stream));
-  // ERI + digest
-  launch_zero(P.d_K4, P.nnz_c, P.stream);
-  launch_zero_u64(P.d_nprim, kNQuartetClass, P.stream);
-  hipEvent_t evc[kNQuartetClass + 1];
-  if (timing)
-    for (auto &e : evc) HIPCHK(hipEventCreate(&e));
+  if (!graph) B.have_counts = true;
+  if (ev) HIPCHK(hipEventRecord(ev[2], B.stream));
   for (int cb = kNPairClass - 1; cb >= 0; --cb)
     for (int ck = cb; ck >= 0; --ck) {
       const int r = region_of(cb, ck);
-      const int64_t n = P.region_q[r + 1] - P.region_q[r];
-      if (timing) HIPCHK(hipEventRecord(evc[r], P.stream));
-      if (n > 0) {
-        if (P.use_coop[r]) {
-          const int Lt = class_la(cb) + class_lb(cb) + class_la(ck) + class_lb(ck);
-          (void)Lt;
-          launch_eri_coop(cb, ck, P.op, P.ds, P.coop[r], P.d_list + P.region_q[r], n, P.d_Dc, P.d_K4,
-                          P.d_nprim + r, P.stream);
-        } else {
-          launch_eri(cb, ck, P.op, P.ds, P.d_list + P.region_q[r], n, P.d_Dc, P.d_K4, P.d_nprim + r, P.stream);
-        }
+      const size_t so = (size_t)r * (n + 1);
+      if (evc) HIPCHK(hipEventRecord(evc[r], B.stream));
+      SegLaunch L{B.d_sys, n, B.d_seg64 + so, B.d_list, B.d_nprim + r, -1, B.stream};
+      if (!graph) L.nq_hint = B.h_seg64[so + n] - B.h_seg64[so];
+      if (P0.use_coop[r])
+        launch_eri_coop(cb, ck, B.op, P0.coop[r], L);
+      else
+        launch_eri(cb, ck, B.op, L);
+      if (B.mixed) {
+        SegLaunch L32{B.d_sys, n, B.d_seg32 + so, B.d_list32, B.d_nprim + r, -1, B.stream};
+        if (!graph) L32.nq_hint = B.h_seg32[so + n] - B.h_seg32[so];
+        if (P0.fp32_kernel[r] == 1 && P0.use_coop[r])
+          launch_eri_coop(cb, ck, B.op, P0.coop[r], L32);
+        else if (P0.fp32_kernel[r] == 1)
+          launch_eri(cb, ck, B.op, L32);
+        else
+          launch_eri_f32(cb, ck, B.op, L32);
       }
-      if (timing && r == 0) HIPCHK(hipEventRecord(evc[kNQuartetClass], P.stream));
+      if (evc && r == 0) HIPCHK(hipEventRecord(evc[kNQuartetClass], B.stream));
     }
-  if (timing) HIPCHK(hipEventRecord(ev[3], P.stream));
-  launch_finalize(P.ds, (int64_t)P.blocks.size(), P.d_blk_IJ, P.d_blk_off, P.d_partner, P.sph, P.d_K4, k_dev, P.stream);
-  if (timing) HIPCHK(hipEventRecord(ev[4], P.stream));
-  HIPCHK(hipGetLastError());
-  if ((flags & (HFX_SYNC | HFX_TIMING)) || info) {
-    HIPCHK(hipStreamSynchronize(P.stream));
-    int32_t err = 0;
-    HIPCHK(hipMemcpy(&err, P.d_err, 4, hipMemcpyDeviceToHost));
-    if (err) return fail(HFX_ERR_UNSUPPORTED, "a ket translation exceeds the quartet encoding range");
+  if (ev) HIPCHK(hipEventRecord(ev[3], B.stream));
+  for (int i = 0; i < n; ++i) {
+    hfx_plan_s &P = *B.plans[i];
+    launch_finalize(P.ds, (int64_t)P.blocks.size(), P.d_blk_IJ, P.d_blk_off, P.d_partner, P.sph, P.d_K4, k_dev[i],
+                    B.stream);
   }
-  if (info) {
-    std::memset(info, 0, sizeof(*info));
-    unsigned long long np[kNQuartetClass];
-    HIPCHK(hipMemcpy(np, P.d_nprim, sizeof(np), hipMemcpyDeviceToHost));
-    info->n_quartets = P.nq_total;
-    double fl = 0.0;
-    for (int cb = 0; cb < kNPairClass; ++cb)
-      for (int ck = 0; ck <= cb; ++ck) {
-        const int r = region_of(cb, ck);
-        info->n_quartets_class[r] = P.region_q[r + 1] - P.region_q[r];
-        info->n_prim_quartets += (int64_t)np[r];
-        double fp, fq;
-        class_flops(class_la(cb), class_lb(cb), class_la(ck), class_lb(ck), P.op, fp, fq);
-        info->flops_class[r] = fp * (double)np[r] + fq * (double)info->n_quartets_class[r];
-        fl += info->flops_class[r];
-      }
-    info->flops = fl;
-    if (timing) {
-      // regions were launched in descending order: class r ends where the next one starts
-      int order[kNQuartetClass], k = 0;
-      for (int cb = kNPairClass - 1; cb >= 0; --cb)
-        for (int ck = cb; ck >= 0; --ck) order[k++] = region_of(cb, ck);
-      for (int i = 0; i < kNQuartetClass; ++i) {
-        hipEvent_t end = (i + 1 < kNQuartetClass) ? evc[order[i + 1]] : evc[kNQuartetClass];
-        float ms;
-        HIPCHK(hipEventElapsedTime(&ms, evc[order[i]], end));
-        info->ms_class[order[i]] = ms;
-      }
+  if (ev) HIPCHK(hipEventRecord(ev[4], B.stream));
+  HIPCHK(hipGetLastError());
+  return HFX_OK;
+}
+
+hfx_status check_err(Batch &B, bool *overflow) {
+  int32_t err[2] = {0, 0};
+  HIPCHK(hipMemcpy(err, B.d_err, sizeof(err), hipMemcpyDeviceToHost));
+  if (overflow) *overflow = (err[0] & 2) != 0;
+  if (err[0] & 1) return fail(HFX_ERR_UNSUPPORTED, "a ket translation exceeds the quartet encoding range");
+  return HFX_OK;
+}
+
+void fill_info(Batch &B, hfx_build_info *info, hipEvent_t *ev, hipEvent_t *evc) {
+  std::memset(info, 0, sizeof(*info));
+  unsigned long long np[kNQuartetClass];
+  if (hipMemcpy(np, B.d_nprim, sizeof(np), hipMemcpyDeviceToHost) != hipSuccess) return;
+  const int n = B.n();
+  hfx_plan_s &P0 = *B.plans[0];
+  double fl = 0.0;
+  for (int cb = 0; cb < kNPairClass; ++cb)
+    for (int ck = 0; ck <= cb; ++ck) {
+      const int r = region_of(cb, ck);
+      const size_t so = (size_t)r * (n + 1);
+      const int64_t q64 = B.h_seg64[so + n] - B.h_seg64[so];
+      const int64_t q32 = B.mixed ? B.h_seg32[so + n] - B.h_seg32[so] : 0;
+      info->n_quartets_class[r] = q64 + q32;
+      info->n_quartets += q64 + q32;
+      if (P0.fp32_kernel[r] == 0) info->n_fp32_quartets += q32;
+      info->n_prim_quartets += (int64_t)np[r];
+      double fp, fq;
+      class_flops(class_la(cb), class_lb(cb), class_la(ck), class_lb(ck), B.op, fp, fq);
+      info->flops_class[r] = fp * (double)np[r] + fq * (double)info->n_quartets_class[r];
+      fl += info->flops_class[r];
     }
-    if (timing) {
+  info->flops = fl;
+  if (ev) {
+    float ms;
+    if (hipEventElapsedTime(&ms, ev[0], ev[1]) == hipSuccess) info->ms_density = ms;
+    if (hipEventElapsedTime(&ms, ev[1], ev[2]) == hipSuccess) info->ms_screen = ms;
+    if (hipEventElapsedTime(&ms, ev[2], ev[3]) == hipSuccess) info->ms_eri = ms;
+    if (hipEventElapsedTime(&ms, ev[3], ev[4]) == hipSuccess) info->ms_finalize = ms;
+    if (hipEventElapsedTime(&ms, ev[0], ev[4]) == hipSuccess) info->ms_total = ms;
+  }
+  if (evc) {
+    int order[kNQuartetClass], k = 0;
+    for (int cb = kNPairClass - 1; cb >= 0; --cb)
+      for (int ck = cb; ck >= 0; --ck) order[k++] = region_of(cb, ck);
+    for (int i = 0; i < kNQuartetClass; ++i) {
+      hipEvent_t end = (i + 1 < kNQuartetClass) ? evc[order[i + 1]] : evc[kNQuartetClass];
       float ms;
-      HIPCHK(hipEventElapsedTime(&ms, ev[0], ev[1]));
-      info->ms_density = ms;
-      HIPCHK(hipEventElapsedTime(&ms, ev[1], ev[2]));
-      info->ms_screen = ms;
-      HIPCHK(hipEventElapsedTime(&ms, ev[2], ev[3]));
-      info->ms_eri = ms;
-      HIPCHK(hipEventElapsedTime(&ms, ev[3], ev[4]));
-      info->ms_finalize = ms;
-      HIPCHK(hipEventElapsedTime(&ms, ev[0], ev[4]));
-      info->ms_total = ms;
+      if (hipEventElapsedTime(&ms, evc[order[i]], end) == hipSuccess) info->ms_class[order[i]] = ms;
     }
+  }
+}
+
+// Run a batch build: eager, or through a captured graph (HFX_GRAPH) that is
+// re-captured when the D/K pointers change and re-run eagerly when the
+// screened list outgrows the capacity fixed at capture time.
+hfx_status run_batch(Batch &B, const double *const *d_dev, double *const *k_dev, uint32_t flags,
+                     hfx_build_info *info) {
+  const int n = B.n();
+  for (int i = 0; i < n; ++i)
+    if (!d_dev[i] || !k_dev[i]) return fail(HFX_ERR_INVALID, "D or K pointer is NULL");
+  for (auto *P : B.plans)
+    if (!P->schwarz_done) {
+      hfx_status st = run_schwarz(*P);
+      if (st != HFX_OK) return st;
+    }
+  const bool timing = (flags & HFX_TIMING) != 0;
+  const bool use_graph = (flags & HFX_GRAPH) != 0 && !timing;
+  if (use_graph && B.have_counts) {
+    bool same = B.gexec && (int)B.g_d.size() == n;
+    for (int i = 0; same && i < n; ++i) same = B.g_d[i] == d_dev[i] && B.g_k[i] == k_dev[i];
+    if (!same) {
+      drop_graph(B);
+      // headroom for the density-dependent list size of later SCF steps
+      hfx_status st = ensure_cap(&B.d_list, &B.cap, B.nq64);
+      if (st == HFX_OK && B.mixed) st = ensure_cap(&B.d_list32, &B.cap32, B.nq32);
+      if (st != HFX_OK) return st;
+      // capture on a private stream (the plan's stream may be the null
+      // stream, which cannot be captured); the graph is launched on the
+      // plan's stream
+      if (!B.cap_stream) HIPCHK(hipStreamCreateWithFlags(&B.cap_stream, hipStreamNonBlocking));
+      HIPCHK(hipStreamSynchronize(B.stream));
+      HIPCHK(hipStreamBeginCapture(B.cap_stream, hipStreamCaptureModeThreadLocal));
+      const hipStream_t user = B.stream;
+      B.stream = B.cap_stream;
+      st = enqueue_build(B, d_dev, k_dev, true, nullptr, nullptr);
+      hipGraph_t g = nullptr;
+      hipError_t e = hipStreamEndCapture(B.cap_stream, &g);
+      B.stream = user;
+      if (st != HFX_OK) {
+        if (g) (void)hipGraphDestroy(g);
+        return st;
+      }
+      if (e != hipSuccess) return fail(HFX_ERR_DEVICE, std::string("graph capture: ") + hipGetErrorString(e));
+      B.graph = g;
+      HIPCHK(hipGraphInstantiate(&B.gexec, B.graph, nullptr, nullptr, 0));
+      B.g_d.assign(d_dev, d_dev + n);
+      B.g_k.assign(k_dev, k_dev + n);
+    }
+    HIPCHK(hipGraphLaunch(B.gexec, B.stream));
+    HIPCHK(hipStreamSynchronize(B.stream));
+    bool overflow = false;
+    hfx_status st = check_err(B, &overflow);
+    if (st != HFX_OK) return st;
+    if (!overflow) {
+      // counts of this build for the report
+      HIPCHK(hipMemcpy(B.h_seg64.data(), B.d_seg64, B.h_seg64.size() * 8, hipMemcpyDeviceToHost));
+      if (B.mixed) HIPCHK(hipMemcpy(B.h_seg32.data(), B.d_seg32, B.h_seg32.size() * 8, hipMemcpyDeviceToHost));
+      B.nq64 = B.h_seg64.back();
+      B.nq32 = B.mixed ? B.h_seg32.back() : 0;
+      if (info) fill_info(B, info, nullptr, nullptr);
+      return HFX_OK;
+    }
+    // the list outgrew the captured capacity: rebuild eagerly, recapture next time
+    drop_graph(B);
+  }
+  hipEvent_t ev[5], evc[kNQuartetClass + 1];
+  if (timing) {
+    for (auto &e : ev) HIPCHK(hipEventCreate(&e));
+    for (auto &e : evc) HIPCHK(hipEventCreate(&e));
+  }
+  hfx_status st = enqueue_build(B, d_dev, k_dev, false, timing ? ev : nullptr, timing ? evc : nullptr);
+  if (st == HFX_OK && ((flags & (HFX_SYNC | HFX_TIMING)) || info)) {
+    HIPCHK(hipStreamSynchronize(B.stream));
+    st = check_err(B, nullptr);
+    if (st == HFX_OK && info) fill_info(B, info, timing ? ev : nullptr, timing ? evc : nullptr);
   }
   if (timing) {
     for (auto &e : ev) (void)hipEventDestroy(e);
     for (auto &e : evc) (void)hipEventDestroy(e);
   }
-  return HFX_OK;
+  return st;
 }
+
+void drop_batches_of(const hfx_plan_s *P) {
+  std::lock_guard<std::mutex> lk(g_batch_mu);
+  for (size_t i = 0; i < g_batches.size();) {
+    Batch *B = g_batches[i];
+    if (std::find(B->plans.begin(), B->plans.end(), P) != B->plans.end()) {
+      (void)hipStreamSynchronize(B->stream);
+      delete B;
+      g_batches.erase(g_batches.begin() + i);
+    } else {
+      ++i;
+    }
+  }
+}
+
+}  // namespace
+
+extern "C" {
 
 hfx_status hfx_build_K(hfx_plan_t plan, const double *d_dev, double *k_dev, uint32_t flags, hfx_build_info *info) {
   if (!valid_plan(plan)) return fail(HFX_ERR_STATE, "invalid or destroyed plan");
-  return build_one(*plan, d_dev, k_dev, flags, info);
+  hfx_plan_s &P = *plan;
+  if (!P.self_batch) {
+    Batch *B = new Batch();
+    hfx_status st = batch_init(*B, {&P});
+    if (st != HFX_OK) {
+      delete B;
+      return st;
+    }
+    P.self_batch = B;
+  }
+  return run_batch(*P.self_batch, &d_dev, &k_dev, flags, info);
 }
 
 hfx_status hfx_build_K_multi(int32_t n, const hfx_plan_t *plans, const double *const *d_dev, double *const *k_dev,
                              uint32_t flags, hfx_build_info *info) {
   if (n < 0 || (n > 0 && (!plans || !d_dev || !k_dev))) return fail(HFX_ERR_INVALID, "bad arguments");
-  for (int i = 0; i < n; ++i)
-    if (!valid_plan(plans[i])) return fail(HFX_ERR_STATE, "invalid or destroyed plan");
-  for (int i = 0; i < n; ++i) {
-    hfx_status st = build_one(*plans[i], d_dev[i], k_dev[i], flags, nullptr);
-    if (st != HFX_OK) return st;
-  }
   if (info) std::memset(info, 0, sizeof(*info));
+  if (n == 0) return HFX_OK;
+  for (int i = 0; i < n; ++i) {
+    if (!valid_plan(plans[i])) return fail(HFX_ERR_STATE, "invalid or destroyed plan");
+    for (int j = 0; j < i; ++j)
+      if (plans[j] == plans[i]) return fail(HFX_ERR_INVALID, "a plan appears twice in one multi build");
+  }
+  // one fused batch per operator (the ERI kernels are specialised on it)
+  for (int op = 0; op <= 1; ++op) {
+    std::vector<hfx_plan_s *> ps;
+    std::vector<const double *> ds;
+    std::vector<double *> ks;
+    for (int i = 0; i < n; ++i)
+      if (plans[i]->op == op) {
+        ps.push_back(plans[i]);
+        ds.push_back(d_dev[i]);
+        ks.push_back(k_dev[i]);
+      }
+    if (ps.empty()) continue;
+    Batch *B = nullptr;
+    {
+      std::lock_guard<std::mutex> lk(g_batch_mu);
+      for (Batch *b : g_batches)
+        if (b->plans == ps) B = b;
+    }
+    if (!B) {
+      B = new Batch();
+      hfx_status st = batch_init(*B, ps);
+      if (st != HFX_OK) {
+        delete B;
+        return st;
+      }
+      std::lock_guard<std::mutex> lk(g_batch_mu);
+      g_batches.push_back(B);
+      // keep the cache bounded
+      if (g_batches.size() > 64) {
+        Batch *old = g_batches.front();
+        (void)hipStreamSynchronize(old->stream);
+        delete old;
+        g_batches.erase(g_batches.begin());
+      }
+    }
+    hfx_build_info sub;
+    hfx_status st = run_batch(*B, ds.data(), ks.data(), flags, info ? &sub : nullptr);
+    if (st != HFX_OK) return st;
+    if (info) {
+      info->n_quartets += sub.n_quartets;
+      info->n_prim_quartets += sub.n_prim_quartets;
+      info->n_fp32_quartets += sub.n_fp32_quartets;
+      info->flops += sub.flops;
+      info->ms_density += sub.ms_density;
+      info->ms_screen += sub.ms_screen;
+      info->ms_eri += sub.ms_eri;
+      info->ms_finalize += sub.ms_finalize;
+      info->ms_total += sub.ms_total;
+      for (int r = 0; r < HFX_N_CLASSES; ++r) {
+        info->n_quartets_class[r] += sub.n_quartets_class[r];
+        info->ms_class[r] += sub.ms_class[r];
+        info->flops_class[r] += sub.flops_class[r];
+      }
+    }
+  }
   return HFX_OK;
 }
 
@@ -888,6 +1172,7 @@ hfx_status hfx_export(hfx_plan_t plan, int32_t what, void *host, int64_t *n) {
   if (!valid_plan(plan)) return fail(HFX_ERR_STATE, "invalid or destroyed plan");
   if (!n) return fail(HFX_ERR_INVALID, "n is NULL");
   hfx_plan_s &P = *plan;
+  Batch *B = P.self_batch;
   switch (what) {
     case 0:
       *n = (int64_t)P.blocks.size();
@@ -897,12 +1182,15 @@ hfx_status hfx_export(hfx_plan_t plan, int32_t what, void *host, int64_t *n) {
       }
       return HFX_OK;
     case 1:
-      *n = P.nq_total;
+    case 5: {
+      const bool f32 = what == 5;
+      *n = B ? (f32 ? B->nq32 : B->nq64) : 0;
       if (host && *n) {
         HIPCHK(hipStreamSynchronize(P.stream));
-        HIPCHK(hipMemcpy(host, P.d_list, *n * 8, hipMemcpyDeviceToHost));
+        HIPCHK(hipMemcpy(host, f32 ? B->d_list32 : B->d_list, *n * 8, hipMemcpyDeviceToHost));
       }
       return HFX_OK;
+    }
     case 2: {
       *n = (int64_t)P.pr_info.size();
       if (host) {
@@ -935,8 +1223,10 @@ hfx_status hfx_plan_destroy(hfx_plan_t plan) {
     std::lock_guard<std::mutex> lk(g_plans_mu);
     g_plans.erase(plan);
   }
+  drop_batches_of(plan);
   (void)hipStreamSynchronize(plan->stream);
-  if (plan->d_list) (void)hipFree(plan->d_list);
+  delete plan->self_batch;
+  plan->self_batch = nullptr;
   plan->mem.release();
   plan->magic = 0;
   delete plan;

@@ -129,8 +129,27 @@ struct DevSys {
   int32_t op;             // 0 Coulomb, 1 erfc
   double omega2;
   double tau;
+  double fp32_cutoff;     // mixed precision: Q_IJ*Q_KL below this -> FP32 recursion
   const double *boys;     // kBoysRows x kBoysCols
+  // per-build state of this plan
+  const double *Dc;       // Cartesian density blocks
+  double *K4;             // Cartesian K accumulator (row-first contributions)
+  int32_t class_start[kNPairClass + 1];  // unique pairs of class c: [class_start[c], class_start[c+1])
 };
+
+// Plan of quartet qi in a fused class segment: seg[i] <= qi < seg[i+1]
+// (seg has nsys + 1 entries; empty plans have seg[i] == seg[i+1]).
+__device__ __forceinline__ int plan_of(const int64_t *__restrict__ seg, int nsys, int64_t qi) {
+  int lo = 0, hi = nsys;
+  while (hi - lo > 1) {
+    const int mid = (lo + hi) >> 1;
+    if (seg[mid] <= qi)
+      lo = mid;
+    else
+      hi = mid;
+  }
+  return lo;
+}
 
 __device__ __forceinline__ int img_index(const DevSys &s, int a, int b, int c) {
   if (a < -s.imgR[0] || a > s.imgR[0] || b < -s.imgR[1] || b > s.imgR[1] || c < -s.imgR[2] ||

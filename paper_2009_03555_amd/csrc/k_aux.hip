@@ -1,7 +1,6 @@
 // Bandwidth-bound kernels around the ERI phase: density transform and
 // P_max (Eq. dmscreening), quartet screening and compaction (Eq. schwarz
 // times P_scr, 8-fold unique enumeration), K finalisation, fills.
-#include <hipcub/hipcub.hpp>
 
 #include "coop.hpp"
 #include "launchers.hpp"
@@ -9,49 +8,56 @@
 namespace hfx {
 
 // --------------------------------------------------------- dispatchers
-void launch_eri(int cb, int ck, int op, const DevSys &s, const uint64_t *list, int64_t nq, const double *Dc,
-                double *K4, unsigned long long *nprim, hipStream_t st) {
-  typedef void (*fn)(int, const DevSys &, const uint64_t *, int64_t, const double *, double *, unsigned long long *,
-                     hipStream_t);
+void launch_eri(int cb, int ck, int op, const SegLaunch &L) {
+  typedef void (*fn)(int, const SegLaunch &);
   static const fn table[kNQuartetClass] = {
       launch_eri_r00, launch_eri_r10, launch_eri_r11, launch_eri_r20, launch_eri_r21, launch_eri_r22,
       launch_eri_r30, launch_eri_r31, launch_eri_r32, launch_eri_r33, launch_eri_r40, launch_eri_r41,
-      launch_eri_r42, launch_eri_r43, launch_eri_r44, launch_eri_r50, launch_eri_r51, launch_eri_r52,
-      launch_eri_r53, launch_eri_r54, launch_eri_r55};
-  if (cb < 0 || cb >= kNPairClass || ck < 0 || ck > cb) return;
-  table[region_of(cb, ck)](op, s, list, nq, Dc, K4, nprim, st);
+      launch_eri_r42, launch_eri_r43, nullptr, launch_eri_r50, launch_eri_r51, nullptr,
+      nullptr, nullptr, nullptr};
+  if (cb < 0 || cb >= kNPairClass || ck < 0 || ck > cb || !table[region_of(cb, ck)]) return;
+  table[region_of(cb, ck)](op, L);
 }
 
-void launch_eri_coop_r42(int op, const DevSys &s, const CoopDev &cd, const uint64_t *l, int64_t n, const double *D,
-                           double *K, unsigned long long *c, hipStream_t st);
-void launch_eri_coop_r43(int op, const DevSys &s, const CoopDev &cd, const uint64_t *l, int64_t n, const double *D,
-                           double *K, unsigned long long *c, hipStream_t st);
-void launch_eri_coop_r44(int op, const DevSys &s, const CoopDev &cd, const uint64_t *l, int64_t n, const double *D,
-                           double *K, unsigned long long *c, hipStream_t st);
-void launch_eri_coop_r51(int op, const DevSys &s, const CoopDev &cd, const uint64_t *l, int64_t n, const double *D,
-                           double *K, unsigned long long *c, hipStream_t st);
-void launch_eri_coop_r52(int op, const DevSys &s, const CoopDev &cd, const uint64_t *l, int64_t n, const double *D,
-                           double *K, unsigned long long *c, hipStream_t st);
-void launch_eri_coop_r53(int op, const DevSys &s, const CoopDev &cd, const uint64_t *l, int64_t n, const double *D,
-                           double *K, unsigned long long *c, hipStream_t st);
-void launch_eri_coop_r54(int op, const DevSys &s, const CoopDev &cd, const uint64_t *l, int64_t n, const double *D,
-                           double *K, unsigned long long *c, hipStream_t st);
-void launch_eri_coop_r55(int op, const DevSys &s, const CoopDev &cd, const uint64_t *l, int64_t n, const double *D,
-                           double *K, unsigned long long *c, hipStream_t st);
+void launch_eri_coop_r42(int op, const CoopDev &cd, const SegLaunch &L);
+void launch_eri_coop_r43(int op, const CoopDev &cd, const SegLaunch &L);
+void launch_eri_coop_r44(int op, const CoopDev &cd, const SegLaunch &L);
+void launch_eri_coop_r51(int op, const CoopDev &cd, const SegLaunch &L);
+void launch_eri_coop_r52(int op, const CoopDev &cd, const SegLaunch &L);
+void launch_eri_coop_r53(int op, const CoopDev &cd, const SegLaunch &L);
+void launch_eri_coop_r54(int op, const CoopDev &cd, const SegLaunch &L);
+void launch_eri_coop_r55(int op, const CoopDev &cd, const SegLaunch &L);
 
-void launch_eri_coop(int cb, int ck, int op, const DevSys &s, const CoopDev &cd, const uint64_t *list, int64_t nq,
-                     const double *Dc, double *K4, unsigned long long *nprim, hipStream_t st) {
+void launch_schwarz_coop_c4(int op, const DevSys *sys1, const CoopDev &cd, int p0, int p1, hipStream_t st);
+void launch_schwarz_coop_c5(int op, const DevSys *sys1, const CoopDev &cd, int p0, int p1, hipStream_t st);
+void launch_schwarz_coop(int cb, int op, const DevSys *sys1, const CoopDev &cd, int p0, int p1, hipStream_t st) {
+  if (cb == 4) launch_schwarz_coop_c4(op, sys1, cd, p0, p1, st);
+  if (cb == 5) launch_schwarz_coop_c5(op, sys1, cd, p0, p1, st);
+}
+
+void launch_eri_coop(int cb, int ck, int op, const CoopDev &cd, const SegLaunch &L) {
   switch (cb * 10 + ck) {
-    case 42: launch_eri_coop_r42(op, s, cd, list, nq, Dc, K4, nprim, st); break;
-    case 43: launch_eri_coop_r43(op, s, cd, list, nq, Dc, K4, nprim, st); break;
-    case 44: launch_eri_coop_r44(op, s, cd, list, nq, Dc, K4, nprim, st); break;
-    case 51: launch_eri_coop_r51(op, s, cd, list, nq, Dc, K4, nprim, st); break;
-    case 52: launch_eri_coop_r52(op, s, cd, list, nq, Dc, K4, nprim, st); break;
-    case 53: launch_eri_coop_r53(op, s, cd, list, nq, Dc, K4, nprim, st); break;
-    case 54: launch_eri_coop_r54(op, s, cd, list, nq, Dc, K4, nprim, st); break;
-    case 55: launch_eri_coop_r55(op, s, cd, list, nq, Dc, K4, nprim, st); break;
+    case 42: launch_eri_coop_r42(op, cd, L); break;
+    case 43: launch_eri_coop_r43(op, cd, L); break;
+    case 44: launch_eri_coop_r44(op, cd, L); break;
+    case 51: launch_eri_coop_r51(op, cd, L); break;
+    case 52: launch_eri_coop_r52(op, cd, L); break;
+    case 53: launch_eri_coop_r53(op, cd, L); break;
+    case 54: launch_eri_coop_r54(op, cd, L); break;
+    case 55: launch_eri_coop_r55(op, cd, L); break;
     default: break;
   }
+}
+
+void launch_eri_f32(int cb, int ck, int op, const SegLaunch &L) {
+  typedef void (*fn)(int, const SegLaunch &);
+  static const fn table[kNQuartetClass] = {
+      launch_eri_f32_r00, launch_eri_f32_r10, launch_eri_f32_r11, launch_eri_f32_r20, launch_eri_f32_r21,
+      launch_eri_f32_r22, launch_eri_f32_r30, launch_eri_f32_r31, launch_eri_f32_r32, launch_eri_f32_r33,
+      launch_eri_f32_r40, launch_eri_f32_r41, launch_eri_f32_r42, launch_eri_f32_r43, nullptr,
+      launch_eri_f32_r50, launch_eri_f32_r51, nullptr, nullptr, nullptr, nullptr};
+  if (cb < 0 || cb >= kNPairClass || ck < 0 || ck > cb || !table[region_of(cb, ck)]) return;
+  table[region_of(cb, ck)](op, L);
 }
 
 void launch_schwarz(int cb, int op, const DevSys &s, int p0, int p1, hipStream_t st) {
@@ -60,8 +66,6 @@ void launch_schwarz(int cb, int op, const DevSys &s, int p0, int p1, hipStream_t
     case 1: launch_schwarz_c1(op, s, p0, p1, st); break;
     case 2: launch_schwarz_c2(op, s, p0, p1, st); break;
     case 3: launch_schwarz_c3(op, s, p0, p1, st); break;
-    case 4: launch_schwarz_c4(op, s, p0, p1, st); break;
-    case 5: launch_schwarz_c5(op, s, p0, p1, st); break;
     default: break;
   }
 }
@@ -215,9 +219,11 @@ __device__ __forceinline__ double pmax_at(const DevSys &s, int I, int J, int a, 
 // visited: (p|p^G) and (p|p^-G) are one orbit of the permutation relations.
 template <typename F>
 __device__ __forceinline__ void visit_kept(const DevSys &s, int p, int q, double Qp, double Qq, double pglob,
-                                           int32_t *err, F &&emit) {
+                                           int mode, int32_t *err, F &&emit) {
   const double qq = Qp * Qq;
   if (!(qq * pglob > s.tau)) return;
+  if (mode == 1 && !(qq >= s.fp32_cutoff)) return;
+  if (mode == 2 && !(qq < s.fp32_cutoff)) return;
   const int4 bi = s.pr_info[p], ki = s.pr_info[q];
   int nB1, nB2, nB3, nD1, nD2, nD3;
   unpack_img8(bi.z, nB1, nB2, nB3);
@@ -264,16 +270,19 @@ __device__ __forceinline__ void visit_kept(const DevSys &s, int p, int q, double
       }
 }
 
-__global__ __launch_bounds__(256) void screen_kernel(DevSys s, const int2 *__restrict__ items, int64_t nitems,
-                                                     const int32_t *__restrict__ class_start,
+__global__ __launch_bounds__(256) void screen_kernel(const DevSys *__restrict__ sys,
+                                                     const int4 *__restrict__ items, int64_t nitems,
                                                      int32_t *__restrict__ counts,
                                                      const int64_t *__restrict__ offsets,
-                                                     uint64_t *__restrict__ out, int32_t *err, int fill) {
+                                                     uint64_t *__restrict__ out, int64_t cap, int32_t *err,
+                                                     int fill, int mode) {
   const int lane = threadIdx.x & 63;
   const int64_t item = (int64_t)blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6);
   if (item >= nitems) return;  // whole wave leaves together
-  const int2 it = items[item];
+  const int4 it = items[item];
   const int r = it.x, p = it.y;
+  const DevSys &s = sys[it.z];
+  const int32_t *class_start = s.class_start;
   int cb = 0;
   while ((cb + 1) * (cb + 2) / 2 <= r) ++cb;
   const int ck = r - cb * (cb + 1) / 2;
@@ -288,7 +297,7 @@ __global__ __launch_bounds__(256) void screen_kernel(DevSys s, const int2 *__res
     double Qq = 0.0;
     if (q < q1) {
       Qq = s.pr_Q[q];
-      visit_kept(s, p, q, Qp, Qq, pglob, err, [&](int, int, int) { ++cnt; });
+      visit_kept(s, p, q, Qp, Qq, pglob, mode, err, [&](int, int, int) { ++cnt; });
     }
     // wave-wide inclusive scan of cnt
     int x = cnt;
@@ -300,8 +309,12 @@ __global__ __launch_bounds__(256) void screen_kernel(DevSys s, const int2 *__res
     const int total = __shfl(x, 63, 64);
     if (fill && q < q1 && cnt) {
       int64_t pos = running + (x - cnt);
-      visit_kept(s, p, q, Qp, Qq, pglob, err, [&](int g1, int g2, int g3) {
-        out[pos++] = pack_quartet((uint32_t)p, (uint32_t)q, pack_img5(g1, g2, g3));
+      visit_kept(s, p, q, Qp, Qq, pglob, mode, err, [&](int g1, int g2, int g3) {
+        if (pos < cap)
+          out[pos] = pack_quartet((uint32_t)p, (uint32_t)q, pack_img5(g1, g2, g3));
+        else
+          atomicOr(err, 2);
+        ++pos;
       });
     }
     running += total;
@@ -309,30 +322,119 @@ __global__ __launch_bounds__(256) void screen_kernel(DevSys s, const int2 *__res
   if (!fill && lane == 0) counts[item] = (int32_t)running;
 }
 
-void launch_screen(const DevSys &s, const int2 *items, int64_t nitems, const int32_t *class_start,
-                   int32_t *counts, const int64_t *offsets, uint64_t *out, int32_t *err, bool fill,
-                   hipStream_t st) {
+void launch_screen(const DevSys *sys, const int4 *items, int64_t nitems, int32_t *counts, const int64_t *offsets,
+                   uint64_t *out, int64_t cap, int32_t *err, bool fill, int mode, hipStream_t st) {
   if (nitems <= 0) return;
   const int64_t blocks = (nitems + 3) / 4;
-  hipLaunchKernelGGL(screen_kernel, dim3((unsigned)blocks), dim3(256), 0, st, s, items, nitems, class_start,
-                     counts, offsets, out, err, fill ? 1 : 0);
+  hipLaunchKernelGGL(screen_kernel, dim3((unsigned)blocks), dim3(256), 0, st, sys, items, nitems, counts, offsets,
+                     out, cap, err, fill ? 1 : 0, mode);
 }
 
-// exclusive scan: offsets[0] = 0, offsets[i+1] = sum_{k<=i} counts[k]
-struct I64Cast {
-  __host__ __device__ int64_t operator()(const int32_t &x) const { return (int64_t)x; }
-};
-
-hipError_t scan_counts(const int32_t *counts, int64_t *offsets, int64_t n, void *tmp, size_t &tmp_bytes,
-                       hipStream_t st) {
-  hipcub::TransformInputIterator<int64_t, I64Cast, const int32_t *> in(counts, I64Cast());
-  hipError_t e = hipSuccess;
-  if (tmp == nullptr) {
-    e = hipcub::DeviceScan::InclusiveSum(nullptr, tmp_bytes, in, offsets + 1, (int)n, st);
-    return e;
+__global__ void gather_bounds_kernel(const int64_t *__restrict__ offsets, const int64_t *__restrict__ seg_items,
+                                     int64_t *__restrict__ seg, int n, int64_t cap) {
+  const int k = blockIdx.x * blockDim.x + threadIdx.x;
+  if (k < n) {
+    const int64_t v = offsets[seg_items[k]];
+    seg[k] = v < cap ? v : cap;
   }
-  launch_zero_u64(reinterpret_cast<unsigned long long *>(offsets), 1, st);
-  return hipcub::DeviceScan::InclusiveSum(tmp, tmp_bytes, in, offsets + 1, (int)n, st);
+}
+
+void launch_gather_bounds(const int64_t *offsets, const int64_t *seg_items, int64_t *seg, int n, int64_t cap,
+                          hipStream_t st) {
+  if (n <= 0) return;
+  hipLaunchKernelGGL(gather_bounds_kernel, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, offsets, seg_items,
+                     seg, n, cap);
+}
+
+__global__ void zero_i32_kernel(int32_t *p, int64_t n) {
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+    p[i] = 0;
+}
+void launch_zero_i32(int32_t *p, int64_t n, hipStream_t st) {
+  if (n <= 0) return;
+  int64_t blocks = (n + 255) / 256;
+  if (blocks > 8192) blocks = 8192;
+  hipLaunchKernelGGL(zero_i32_kernel, dim3((unsigned)blocks), dim3(256), 0, st, p, n);
+}
+
+// Exclusive scan of int32 counts into int64 offsets (offsets[0] = 0,
+// offsets[i+1] = sum_{k<=i} counts[k]) in three plain kernels: tile sums,
+// scan of the tile sums, tile-local scan plus tile base.  Only kernel nodes,
+// so the sequence can sit inside a captured graph.
+constexpr int kScanThreads = 256;
+constexpr int kScanPer = 4;
+constexpr int kScanTile = kScanThreads * kScanPer;
+
+__device__ __forceinline__ int64_t block_incl_scan(int64_t v, int64_t *sh, int64_t *total = nullptr) {
+  const int t = threadIdx.x;
+  sh[t] = v;
+  __syncthreads();
+  for (int d = 1; d < kScanThreads; d <<= 1) {
+    const int64_t add = t >= d ? sh[t - d] : 0;
+    __syncthreads();
+    sh[t] += add;
+    __syncthreads();
+  }
+  const int64_t r = sh[t];
+  if (total) *total = sh[kScanThreads - 1];
+  __syncthreads();
+  return r;
+}
+
+__global__ __launch_bounds__(kScanThreads) void scan_tile_sums(const int32_t *__restrict__ counts, int64_t n,
+                                                                int64_t *__restrict__ tiles) {
+  __shared__ int64_t sh[kScanThreads];
+  const int64_t base = (int64_t)blockIdx.x * kScanTile + (int64_t)threadIdx.x * kScanPer;
+  int64_t v = 0;
+  for (int k = 0; k < kScanPer; ++k)
+    if (base + k < n) v += counts[base + k];
+  const int64_t incl = block_incl_scan(v, sh);
+  if (threadIdx.x == kScanThreads - 1) tiles[blockIdx.x] = incl;
+}
+
+// one block: exclusive scan of the tile sums in place
+__global__ __launch_bounds__(kScanThreads) void scan_tiles(int64_t *__restrict__ tiles, int64_t ntiles) {
+  __shared__ int64_t sh[kScanThreads];
+  int64_t carry = 0;
+  for (int64_t b0 = 0; b0 < ntiles; b0 += kScanThreads) {
+    const int64_t i = b0 + threadIdx.x;
+    const int64_t v = i < ntiles ? tiles[i] : 0;
+    int64_t tot;
+    const int64_t incl = block_incl_scan(v, sh, &tot);
+    if (i < ntiles) tiles[i] = carry + incl - v;
+    carry += tot;
+  }
+}
+
+__global__ __launch_bounds__(kScanThreads) void scan_apply(const int32_t *__restrict__ counts, int64_t n,
+                                                            const int64_t *__restrict__ tiles,
+                                                            int64_t *__restrict__ offsets) {
+  __shared__ int64_t sh[kScanThreads];
+  const int64_t base = (int64_t)blockIdx.x * kScanTile + (int64_t)threadIdx.x * kScanPer;
+  int64_t c[kScanPer];
+  int64_t v = 0;
+  for (int k = 0; k < kScanPer; ++k) {
+    c[k] = base + k < n ? counts[base + k] : 0;
+    v += c[k];
+  }
+  int64_t run = block_incl_scan(v, sh) - v + tiles[blockIdx.x];
+  for (int k = 0; k < kScanPer; ++k) {
+    run += c[k];
+    if (base + k < n) offsets[base + k + 1] = run;
+  }
+  if (blockIdx.x == 0 && threadIdx.x == 0) offsets[0] = 0;
+}
+
+hipError_t scan_counts(const int32_t *counts, int64_t *offsets, int64_t n, int64_t *tiles, hipStream_t st) {
+  if (n <= 0) {
+    launch_zero_u64(reinterpret_cast<unsigned long long *>(offsets), 1, st);
+    return hipGetLastError();
+  }
+  const int64_t nt = (n + kScanTile - 1) / kScanTile;
+  hipLaunchKernelGGL(scan_tile_sums, dim3((unsigned)nt), dim3(kScanThreads), 0, st, counts, n, tiles);
+  hipLaunchKernelGGL(scan_tiles, dim3(1), dim3(kScanThreads), 0, st, tiles, nt);
+  hipLaunchKernelGGL(scan_apply, dim3((unsigned)nt), dim3(kScanThreads), 0, st, counts, n, tiles, offsets);
+  return hipGetLastError();
 }
 
 }  // namespace hfx

@@ -8,9 +8,19 @@
 
 namespace hfx {
 
+// One class-segment launch over a fused quartet list.
+struct SegLaunch {
+  const DevSys *sys;            // device array of nsys plan descriptors
+  int nsys;
+  const int64_t *seg;           // device: nsys + 1 segment bounds of this class
+  const uint64_t *list;         // fused quartet list
+  unsigned long long *nprim;    // device counter of primitive quartets (this class)
+  int64_t nq_hint;              // quartets if known on the host, -1 if not
+  hipStream_t stream;
+};
+
 #define HFX_DECL_R(CB, CK)                                                                             \
-  void launch_eri_r##CB##CK(int op, const DevSys &s, const uint64_t *list, int64_t nq, const double *Dc,  \
-                            double *K4, unsigned long long *nprim, hipStream_t st);
+  void launch_eri_r##CB##CK(int op, const SegLaunch &L);
 HFX_DECL_R(0, 0)
 HFX_DECL_R(1, 0)
 HFX_DECL_R(1, 1)
@@ -25,25 +35,43 @@ HFX_DECL_R(4, 0)
 HFX_DECL_R(4, 1)
 HFX_DECL_R(4, 2)
 HFX_DECL_R(4, 3)
-HFX_DECL_R(4, 4)
 HFX_DECL_R(5, 0)
 HFX_DECL_R(5, 1)
-HFX_DECL_R(5, 2)
-HFX_DECL_R(5, 3)
-HFX_DECL_R(5, 4)
-HFX_DECL_R(5, 5)
 #undef HFX_DECL_R
+#define HFX_DECL_F32(CB, CK)                                                                           \
+  void launch_eri_f32_r##CB##CK(int op, const SegLaunch &L);
+HFX_DECL_F32(0, 0)
+HFX_DECL_F32(1, 0)
+HFX_DECL_F32(1, 1)
+HFX_DECL_F32(2, 0)
+HFX_DECL_F32(2, 1)
+HFX_DECL_F32(2, 2)
+HFX_DECL_F32(3, 0)
+HFX_DECL_F32(3, 1)
+HFX_DECL_F32(3, 2)
+HFX_DECL_F32(3, 3)
+HFX_DECL_F32(4, 0)
+HFX_DECL_F32(4, 1)
+HFX_DECL_F32(4, 2)
+HFX_DECL_F32(4, 3)
+HFX_DECL_F32(5, 0)
+HFX_DECL_F32(5, 1)
+#undef HFX_DECL_F32
 void launch_schwarz_c0(int op, const DevSys &s, int p0, int p1, hipStream_t st);
 void launch_schwarz_c1(int op, const DevSys &s, int p0, int p1, hipStream_t st);
 void launch_schwarz_c2(int op, const DevSys &s, int p0, int p1, hipStream_t st);
 void launch_schwarz_c3(int op, const DevSys &s, int p0, int p1, hipStream_t st);
-void launch_schwarz_c4(int op, const DevSys &s, int p0, int p1, hipStream_t st);
-void launch_schwarz_c5(int op, const DevSys &s, int p0, int p1, hipStream_t st);
 
 
-void launch_eri(int cb, int ck, int op, const DevSys &s, const uint64_t *list, int64_t nq, const double *Dc,
-                double *K4, unsigned long long *nprim, hipStream_t st);
+// classes evaluated only by the cooperative kernels (their one-lane recursion
+// would spill): (dp|dp), (dd|pp), (dd|ds), (dd|dp), (dd|dd)
+__host__ __device__ constexpr bool register_available(int cb, int ck) {
+  return !((cb == 4 && ck == 4) || (cb == 5 && ck >= 2));
+}
+void launch_eri(int cb, int ck, int op, const SegLaunch &L);
+void launch_eri_f32(int cb, int ck, int op, const SegLaunch &L);
 void launch_schwarz(int cb, int op, const DevSys &s, int p0, int p1, hipStream_t st);
+void launch_zero_i32(int32_t *p, int64_t n, hipStream_t st);
 
 // D (boundary basis) -> D_cart and P_max per block (canonical block decides,
 // partner copies); global max into s.pmax_global.
@@ -57,11 +85,19 @@ void launch_zero(double *p, int64_t n, hipStream_t st);
 void launch_zero_u64(unsigned long long *p, int64_t n, hipStream_t st);
 // Screening: one wave per item (region, bra pair).  count pass writes
 // counts[item]; fill pass writes the quartets at offsets[item].
-void launch_screen(const DevSys &s, const int2 *items, int64_t nitems, const int32_t *class_start,
-                   int32_t *counts, const int64_t *offsets, uint64_t *out, int32_t *err, bool fill,
-                   hipStream_t st);
+// Screening over fused work items (region, bra pair, plan).  mode: 0 every
+// kept quartet, 1 only Q_IJ*Q_KL >= fp32_cutoff (FP64 path), 2 only
+// Q_IJ*Q_KL < fp32_cutoff (FP32 path).  Count pass writes counts[item]; fill
+// pass writes at offsets[item] and never at or beyond cap (sets err bit 2).
+void launch_screen(const DevSys *sys, const int4 *items, int64_t nitems, int32_t *counts, const int64_t *offsets,
+                   uint64_t *out, int64_t cap, int32_t *err, bool fill, int mode, hipStream_t st);
+// seg[k] = min(offsets[seg_items[k]], cap), k < n: class-segment bounds on
+// the device, clamped to the list capacity so that the ERI kernels of a
+// replayed graph never read past the list when the screened count overflows
+void launch_gather_bounds(const int64_t *offsets, const int64_t *seg_items, int64_t *seg, int n, int64_t cap,
+                          hipStream_t st);
 // exclusive prefix sum of int32 counts into int64 offsets (n+1 entries)
-hipError_t scan_counts(const int32_t *counts, int64_t *offsets, int64_t n, void *tmp, size_t &tmp_bytes,
-                       hipStream_t st);
+// tiles: device scratch of at least (n + 1023) / 1024 entries
+hipError_t scan_counts(const int32_t *counts, int64_t *offsets, int64_t n, int64_t *tiles, hipStream_t st);
 
 }  // namespace hfx

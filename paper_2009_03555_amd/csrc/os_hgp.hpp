@@ -275,13 +275,16 @@ __device__ __forceinline__ void hrr(const double *acc, const double *AB, const d
   }
 }
 
-// --------------------------------------------------- primitive loop (FP64)
+// ------------------------------------------------------- primitive loop
 // Sum of [e0|f0] over the primitive quartets t = lane, lane+stride, ... of
 // the nb x nk grid.  Ket centres are shifted by g (lattice translation).
-template <class C, int OP>
+// T is the type of the recursion and of the primitive sum: double, or float
+// for the mixed-precision path (the ladder, including the Boys function, and
+// the prefactor are always evaluated in double and rounded once).
+template <class C, int OP, typename T = double>
 __device__ __forceinline__ void prim_sum(const DevSys &s, const double *__restrict__ ppb, int nb,
                                          const double *__restrict__ ppk, int nk, double gx, double gy,
-                                         double gz, int lane, int stride, double *acc) {
+                                         double gz, int lane, int stride, T *acc) {
   constexpr int L = C::L;
   const int n = nb * nk;
   for (int t = lane; t < n; t += stride) {
@@ -295,18 +298,21 @@ __device__ __forceinline__ void prim_sum(const DevSys &s, const double *__restri
     const double ize = 1.0 / ze;
     const double rho = zeta * eta * ize;
     const double PQx = Px - Qx, PQy = Py - Qy, PQz = Pz - Qz;
-    const double T = rho * (PQx * PQx + PQy * PQy + PQz * PQz);
+    const double T2 = rho * (PQx * PQx + PQy * PQy + PQz * PQz);
     // 2 pi^(5/2) / (zeta eta sqrt(zeta + eta)) K_ab K_cd
     const double pref = 34.986836655249725693 / (zeta * eta * sqrt(ze)) * b[7] * k[7];
     double G[L + 1];
-    ladder<L, OP>(T, rho, s.omega2, pref, s.boys, G);
+    ladder<L, OP>(T2, rho, s.omega2, pref, s.boys, G);
     const double fe = eta * ize, fz = zeta * ize;
-    double PA[3] = {b[4], b[5], b[6]};
-    double WP[3] = {-fe * PQx, -fe * PQy, -fe * PQz};
-    double QC[3] = {k[4], k[5], k[6]};
-    double WQ[3] = {fz * PQx, fz * PQy, fz * PQz};
-    const double o2z = 0.5 / zeta, o2e = 0.5 / eta;
-    vrr_add<C, double>(G, PA, WP, QC, WQ, o2z, rho / zeta, o2e, rho / eta, 0.5 * ize, acc);
+    T Gt[L + 1];
+#pragma unroll
+    for (int m = 0; m <= L; ++m) Gt[m] = (T)G[m];
+    T PA[3] = {(T)b[4], (T)b[5], (T)b[6]};
+    T WP[3] = {(T)(-fe * PQx), (T)(-fe * PQy), (T)(-fe * PQz)};
+    T QC[3] = {(T)k[4], (T)k[5], (T)k[6]};
+    T WQ[3] = {(T)(fz * PQx), (T)(fz * PQy), (T)(fz * PQz)};
+    vrr_add<C, T>(Gt, PA, WP, QC, WQ, (T)(0.5 / zeta), (T)(rho / zeta), (T)(0.5 / eta), (T)(rho / eta),
+                  (T)(0.5 * ize), acc);
   }
 }
 

@@ -22,6 +22,7 @@ STATUS_NAMES = ["HFX_OK", "HFX_ERR_INVALID", "HFX_ERR_OOM", "HFX_ERR_DEVICE", "H
                 "HFX_ERR_UNSUPPORTED"]
 HFX_SYNC = 1
 HFX_TIMING = 2
+HFX_GRAPH = 4
 N_CLASSES = 21
 OPS = {"coulomb": 0, "erfc": 1}
 PRECISIONS = {"fp64": 0, "mixed": 1}
@@ -195,7 +196,7 @@ class Plan:
         _check(lib().hfx_export(self._h, what, None, ctypes.byref(n)))
         if what == 0 or what == 3:
             out = np.zeros(max(n.value, 1), dtype=np.float64)
-        elif what == 1:
+        elif what in (1, 5):
             out = np.zeros(max(n.value, 1), dtype=np.uint64)
         else:
             out = np.zeros((max(n.value, 1), 6), dtype=np.int32)
@@ -214,12 +215,16 @@ class Plan:
             pass
 
 
-def build_K_multi(plans: Sequence[Plan], Ds, Ks, flags: int = 0):
+def build_K_multi(plans: Sequence[Plan], Ds, Ks, flags: int = 0, info: bool = False):
+    """``hfx_build_K_multi``: every plan's K from its D in fused launches."""
     n = len(plans)
     hs = (ctypes.c_void_p * n)(*[p.handle.value for p in plans])
     ds = (ctypes.c_void_p * n)(*[_ptr(d) for d in Ds])
     ks = (ctypes.c_void_p * n)(*[_ptr(k) for k in Ks])
-    _check(lib().hfx_build_K_multi(n, hs, ds, ks, ctypes.c_uint32(flags), None))
+    inf = hfx_build_info() if info else None
+    _check(lib().hfx_build_K_multi(n, hs, ds, ks, ctypes.c_uint32(flags),
+                                   ctypes.byref(inf) if inf is not None else None))
+    return inf.as_dict() if inf is not None else None
 
 
 def unpack_quartets(q: np.ndarray) -> np.ndarray:

@@ -197,3 +197,53 @@ def test_destroyed_plan_is_rejected():
     st = hfx.lib().hfx_build_K(hfx.ctypes.c_void_p(h), hfx.ctypes.c_void_p(D.data_ptr()),
                                hfx.ctypes.c_void_p(D.data_ptr()), 0, None)
     assert st == hfx.HFX_ERR_STATE
+
+
+# ------------------------------------------------------------ mixed precision
+TOL_MIXED = 1e-7
+
+
+def _build(system, D=None):
+    plan = hfx.Plan(system)
+    if D is None:
+        D = _density(system, plan.blocks)
+    Dd = torch.from_numpy(D).to(DEV)
+    Kd = torch.zeros_like(Dd)
+    info = plan.build_K(Dd, Kd, flags=hfx.HFX_SYNC, info=True)
+    return plan, D, Kd.cpu().numpy(), info
+
+
+@pytest.mark.parametrize("cutoff", [1e-6, 1e-2])
+def test_mixed_precision_periodic_erfc(cutoff):
+    s64 = _tiny_cell(seed=91)
+    smx = s64.with_(precision="mixed", fp32_cutoff=cutoff)
+    p64, D, K64, i64 = _build(s64)
+    pmx, _, Kmx, imx = _build(smx, D)
+    assert imx["n_quartets"] == i64["n_quartets"]
+    assert imx["n_fp32_quartets"] > 0
+    o = oracle.Oracle(s64)
+    o.set_density(D)
+    Kref, _ = o.build_K()
+    err_o = np.max(np.abs(Kmx - Kref))
+    err_g = np.max(np.abs(Kmx - K64))
+    print(f"mixed cutoff {cutoff}: {imx['n_fp32_quartets']}/{imx['n_quartets']} FP32, "
+          f"max|dK| vs oracle {err_o:.2e}, vs FP64 GPU {err_g:.2e}")
+    assert err_o <= TOL_MIXED
+    assert err_g <= TOL_MIXED
+    # the two lists together are the FP64 list
+    both = np.concatenate([pmx.export(1), pmx.export(5)])
+    assert np.array_equal(np.sort(both), np.sort(p64.export(1)))
+
+
+def test_mixed_precision_cluster_config3_recipe():
+    # small enough for the oracle: 5 atoms (3 heavy, 2 light), 3 primitives
+    s = systems.random_cluster(5, 2024, nprim=3, op="coulomb", tau=1e-10, precision="mixed",
+                               fp32_cutoff=1e-6)
+    plan, D, K, info = _build(s)
+    o = oracle.Oracle(s)
+    o.set_density(D)
+    Kref, _ = o.build_K()
+    err = np.max(np.abs(K - Kref))
+    print(f"cluster5 mixed: {info['n_fp32_quartets']}/{info['n_quartets']} FP32, max|dK| {err:.2e}")
+    assert info["n_fp32_quartets"] > 0
+    assert err <= TOL_MIXED
