@@ -1,0 +1,308 @@
+// Lane-per-component ERI + digest kernel for high angular-momentum classes.
+//
+// The Obara-Saika VRR to [e0|f0] is split by electron.  One side (the "lane
+// side", the pair class with the lower total angular momentum) is spread over
+// the lanes of a group: lane s owns the Cartesian component s of that side's
+// levels 0..LS.  The other side (the "grow side") is built last, entirely in
+// that lane's registers, by the compile-time-unrolled recursion on the grow
+// index: every operand of the grow-side step is lane-local except the
+// electron-coupling term N_i(s)/(2(zeta+eta)) [s - 1_i, g]^(m+1), which one
+// LDS read fetches from the lane owning s - 1_i.  A group needs
+// noff(LS + 1) lanes; 64 / that many groups evaluate different primitive
+// quartets of the same contracted quartet side by side.  Each lane sums its
+// targets [s, g]^(0) over the primitive quartets in registers; the groups are
+// combined by cross-lane reads once per contracted quartet, followed by the
+// HGP HRR and the digest in LDS.
+//
+// Before the grow-side build, each lane needs [s, 0]^(m): it walks the chain
+// of ancestors of s (the unique build path of the lane side's recursion)
+// itself, which costs no more wave time than a shared level-by-level build.
+#pragma once
+#include "eri_wave.hpp"
+#include "launchers.hpp"
+
+namespace hfx {
+
+template <int CB, int CK, bool KL>
+struct LaneShape {
+  static constexpr int LA = class_la(CB), LB = class_lb(CB), LC = class_la(CK), LD = class_lb(CK);
+  static constexpr int EB = LA + LB, FK = LC + LD, L = EB + FK;
+  static constexpr int LS = KL ? FK : EB;  // lane side: components of levels 0..LS
+  static constexpr int SL = KL ? LC : LA;  // lowest lane-side level among the targets
+  static constexpr int LG = KL ? EB : FK;  // grow side, built in registers
+  static constexpr int GL = KL ? LA : LC;  // lowest grow-side level among the targets
+  static constexpr int NS = noff(LS + 1);
+  static constexpr int NGRP = 64 / NS;
+  static constexpr int NGT = noff(LG + 1) - noff(GL);
+  static constexpr int NE = noff(EB + 1) - noff(LA), NF = noff(FK + 1) - noff(LC);
+  static constexpr int NA = ncart(LA), NB = ncart(LB), NC = ncart(LC), ND = ncart(LD);
+  // primitive quartets staged per batch: a multiple of the group count
+  static constexpr int NBATCH = NGRP * ((32 + NGRP - 1) / NGRP);
+  // register slots V[lv][c][m], m = 0..LG-lv
+  __host__ __device__ static constexpr int vw(int lv) { return LG - lv + 1; }
+  __host__ __device__ static constexpr int vo(int lv, int c, int m) {
+    int s = 0;
+    for (int l = 0; l < lv; ++l) s += ncart(l) * vw(l);
+    return s + c * vw(lv) + m;
+  }
+  static constexpr int NV = vo(LG + 1, 0, 0);
+  // published values of one level: (c, m = 1..LG-lv) at c*(LG-lv) + m-1, for
+  // each of the 64 lanes; two buffers alternate by level
+  __host__ __device__ static constexpr int pbl() {
+    int m = 1;
+    for (int l = 0; l < LG; ++l) m = cmax(m, ncart(l) * (LG - l));
+    return m;
+  }
+  // HRR ping-pong region: twice the largest HRR level (same as the op lists)
+  __host__ __device__ static constexpr int hrr_r() {
+    int r = NE * NF;
+    for (int b = 1; b <= LB; ++b) r = cmax(r, (noff(EB - b + 1) - noff(LA)) * ncart(b) * NF);
+    for (int d = 1; d <= LD; ++d) r = cmax(r, NA * NB * (noff(FK - d + 1) - noff(LC)) * ncart(d));
+    return r;
+  }
+  template <typename TV>
+  __host__ __device__ static constexpr int work_doubles() {
+    return cmax(2 * hrr_r(), (2 * pbl() * 64 * (int)sizeof(TV) + 7) / 8);
+  }
+  template <typename TV>
+  __host__ __device__ static constexpr size_t lds_bytes() {
+    return (size_t)(work_doubles<TV>() + NBATCH * kCoopStage) * sizeof(double);
+  }
+};
+
+template <typename TV>
+__device__ __forceinline__ TV sel3v(int d, TV x, TV y, TV z) {
+  return d == 0 ? x : (d == 1 ? y : z);
+}
+
+template <int CB, int CK, int OP, bool KL, typename TV>
+__global__ __launch_bounds__(64) void eri_lane_kernel(const DevSys *__restrict__ sys, int nsys,
+                                                      const int64_t *__restrict__ seg, CoopDev cd,
+                                                      const uint64_t *__restrict__ list,
+                                                      unsigned long long *__restrict__ nprim) {
+  using SH = LaneShape<CB, CK, KL>;
+  constexpr int L = SH::L, LS = SH::LS, LG = SH::LG, GL = SH::GL, NS = SH::NS, NGRP = SH::NGRP;
+  constexpr int NGT = SH::NGT, NF = SH::NF, PBL = SH::pbl(), NBATCH = SH::NBATCH;
+  // stage slots of the lane side and of the grow side
+  constexpr int XS = KL ? 15 : 9, YS = KL ? 18 : 12, OS2 = KL ? 23 : 21, RS = KL ? 24 : 22;
+  constexpr int XG = KL ? 9 : 15, YG = KL ? 12 : 18, OG2 = KL ? 21 : 23, RG = KL ? 22 : 24;
+  extern __shared__ double W[];
+  TV *pub = reinterpret_cast<TV *>(W);
+  double *stage = W + SH::template work_doubles<TV>();
+  const int lane = threadIdx.x;
+  const bool active = lane < NGRP * NS;
+  const int grp = active ? lane / NS : 0;
+  const int sidx = active ? lane - grp * NS : 0;
+  int ns = 0;
+  while (noff(ns + 1) <= sidx) ++ns;
+  const C3 sc = cart_of(ns, sidx - noff(ns));
+  // electron-coupling term: power s_i and the lane of s - 1_i
+  int src[3];
+  TV npow[3];
+#pragma unroll
+  for (int i = 0; i < 3; ++i) {
+    const int n = pw(sc, i);
+    npow[i] = (TV)n;
+    src[i] = n > 0 ? grp * NS + noff(ns - 1) + cidx(sub1(sc, i)) : lane;
+  }
+  // ancestor chain of s: step k builds level k from level k-1 in direction
+  // cdir[k-1]; cpow[k-1] is the parent's power in that direction
+  int cdir[LS > 0 ? LS : 1];
+  TV cpow[LS > 0 ? LS : 1];
+  {
+    C3 cur = sc;
+#pragma unroll
+    for (int k = LS; k >= 1; --k) {
+      int d = 0, np = 0;
+      if (k <= ns) {
+        d = dir_of(cur);
+        const C3 par = sub1(cur, d);
+        np = pw(par, d);
+        cur = par;
+      }
+      cdir[k - 1] = d;
+      cpow[k - 1] = (TV)np;
+    }
+  }
+
+  unsigned long long prims = 0;
+  const int64_t q0 = seg[0], q1 = seg[nsys];
+  for (int64_t qi = q0 + blockIdx.x; qi < q1; qi += gridDim.x) {
+    const DevSys &s = sys[nsys > 1 ? plan_of(seg, nsys, qi) : 0];
+    const uint64_t q = list[qi];
+    const int bra = (int)(q & 0xFFFFFFull), ket = (int)((q >> 24) & 0xFFFFFFull);
+    int g1, g2, g3;
+    unpack_img5((uint32_t)(q >> 48), g1, g2, g3);
+    const int4 bi = s.pr_info[bra], ki = s.pr_info[ket];
+    const int2 bpp = s.pr_pp[bra], kpp = s.pr_pp[ket];
+    double gx = 0.0, gy = 0.0, gz = 0.0;
+    if (s.periodic) {
+      gx = g1 * s.lat[0] + g2 * s.lat[3] + g3 * s.lat[6];
+      gy = g1 * s.lat[1] + g2 * s.lat[4] + g3 * s.lat[7];
+      gz = g1 * s.lat[2] + g2 * s.lat[5] + g3 * s.lat[8];
+    }
+    const double *ppb = s.pp + (int64_t)bpp.x * kPP;
+    const double *ppk = s.pp + (int64_t)kpp.x * kPP;
+    const int nk = kpp.y;
+    const int n = bpp.y * nk;
+    prims += (unsigned long long)n;
+    TV acc[NGT];
+#pragma unroll
+    for (int k = 0; k < NGT; ++k) acc[k] = (TV)0;
+
+    for (int t0 = 0; t0 < n; t0 += NBATCH) {
+      stage_prims<L, OP>(stage, lane, NBATCH, t0, n, nk, ppb, ppk, gx, gy, gz, s);
+      __syncthreads();
+      const int cnt = (n - t0) < NBATCH ? (n - t0) : NBATCH;
+      for (int u0 = 0; u0 < cnt; u0 += NGRP) {
+        const int u = u0 + grp;
+        const bool live = u < cnt;
+        const double *st = stage + (live ? u : 0) * kCoopStage;
+        const TV sx0 = (TV)st[XS], sx1 = (TV)st[XS + 1], sx2 = (TV)st[XS + 2];
+        const TV sy0 = (TV)st[YS], sy1 = (TV)st[YS + 1], sy2 = (TV)st[YS + 2];
+        const TV o2s = (TV)st[OS2], rs = (TV)st[RS];
+        const TV gX[3] = {(TV)st[XG], (TV)st[XG + 1], (TV)st[XG + 2]};
+        const TV gY[3] = {(TV)st[YG], (TV)st[YG + 1], (TV)st[YG + 2]};
+        const TV o2g = (TV)st[OG2], rg = (TV)st[RG];
+        const TV o2ze = (TV)st[25];
+        const TV xc[3] = {npow[0] * o2ze, npow[1] * o2ze, npow[2] * o2ze};
+
+        // ---- lane side: [s, 0]^(m), m = 0..LG, along the ancestor chain
+        TV cur[L + 1], prv[L + 1], res[LG + 1];
+#pragma unroll
+        for (int m = 0; m <= L; ++m) cur[m] = live ? (TV)st[m] : (TV)0;
+#pragma unroll
+        for (int m = 0; m <= L; ++m) prv[m] = (TV)0;
+#pragma unroll
+        for (int m = 0; m <= LG; ++m) res[m] = cur[m];
+        sfor<1, LS + 1>([&](auto k_) {
+          constexpr int k = decltype(k_)::value;
+          constexpr int MK = L - k;
+          const int d = cdir[k - 1];
+          const TV X = sel3v(d, sx0, sx1, sx2), Y = sel3v(d, sy0, sy1, sy2);
+          const TV cn = cpow[k - 1] * o2s;
+          TV nw[MK + 1];
+#pragma unroll
+          for (int m = 0; m <= MK; ++m) {
+            TV v = fma(Y, cur[m + 1], X * cur[m]);
+            if constexpr (k >= 2) v = fma(cn, fma(-rs, prv[m + 1], prv[m]), v);
+            nw[m] = v;
+          }
+          const bool take = (k == ns);
+#pragma unroll
+          for (int m = 0; m <= LG; ++m) res[m] = take ? nw[m] : res[m];
+#pragma unroll
+          for (int m = 0; m <= MK + 1; ++m) prv[m] = cur[m];
+#pragma unroll
+          for (int m = 0; m <= MK; ++m) cur[m] = nw[m];
+        });
+
+        // ---- grow side in registers, electron coupling through LDS
+        TV V[SH::NV];
+#pragma unroll
+        for (int m = 0; m <= LG; ++m) V[SH::vo(0, 0, m)] = res[m];
+        if constexpr (GL == 0) acc[0] += V[0];
+        if constexpr (LG > 0) {
+#pragma unroll
+          for (int m = 1; m <= LG; ++m) pub[(m - 1) * 64 + lane] = V[SH::vo(0, 0, m)];
+          __syncthreads();
+        }
+        sfor<1, LG + 1>([&](auto lv_) {
+          constexpr int lv = decltype(lv_)::value;
+          constexpr int MR = LG - lv;
+          constexpr int rb = ((lv - 1) & 1) * PBL, wb = (lv & 1) * PBL;
+          sfor<0, ncart(lv)>([&](auto c_) {
+            constexpr int c = decltype(c_)::value;
+            constexpr C3 t = cart_of(lv, c);
+            constexpr int i = dir_of(t);
+            constexpr C3 p = sub1(t, i);
+            constexpr int np = pw(p, i);
+            constexpr int pc = cidx(p);
+            constexpr int ppc = np > 0 ? cidx(sub1(p, i)) : 0;
+            TV R[MR + 1];
+#pragma unroll
+            for (int m = 0; m <= MR; ++m) R[m] = pub[(rb + pc * (MR + 1) + m) * 64 + src[i]];
+#pragma unroll
+            for (int m = 0; m <= MR; ++m) {
+              TV v = fma(gY[i], V[SH::vo(lv - 1, pc, m + 1)], gX[i] * V[SH::vo(lv - 1, pc, m)]);
+              if constexpr (np > 0)
+                v = fma((TV)np * o2g, fma(-rg, V[SH::vo(lv - 2, ppc, m + 1)], V[SH::vo(lv - 2, ppc, m)]), v);
+              V[SH::vo(lv, c, m)] = fma(xc[i], R[m], v);
+            }
+            if constexpr (lv >= GL) acc[noff(lv) + c - noff(GL)] += V[SH::vo(lv, c, 0)];
+          });
+          if constexpr (lv < LG) {
+            sfor<0, ncart(lv)>([&](auto c_) {
+              constexpr int c = decltype(c_)::value;
+#pragma unroll
+              for (int m = 1; m <= MR; ++m) pub[(wb + c * MR + m - 1) * 64 + lane] = V[SH::vo(lv, c, m)];
+            });
+            __syncthreads();
+          }
+        });
+      }
+      __syncthreads();  // the stage is rewritten by the next batch
+    }
+    // ---- sum the groups, contracted [e0|f0] into W (e-major), HRR, digest
+    sfor<0, NGT>([&](auto k_) {
+      constexpr int k = decltype(k_)::value;
+      TV tot = acc[k];
+      if constexpr (NGRP > 1) {
+#pragma unroll
+        for (int g = 1; g < NGRP; ++g) tot += __shfl(acc[k], g * NS + sidx);
+      }
+      if (active && grp == 0 && ns >= SH::SL) {
+        const int ks = sidx - noff(SH::SL);
+        const int tt = KL ? (k * NF + ks) : (ks * NF + k);
+        W[tt] = (double)tot;
+      }
+    });
+    __syncthreads();
+    hrr_w<CB, CK>(W, cd, s, bra, ket, lane);
+    digest_w<CB, CK>(W + cd.out_base, s, bi, ki, bra, ket, g1, g2, g3, lane);
+    __syncthreads();
+  }
+  if (lane == 0 && prims) atomicAdd(nprim, prims);
+}
+
+// lane side: the pair class with the lower total angular momentum
+template <int CB, int CK>
+constexpr bool lane_ket() {
+  return class_la(CK) + class_lb(CK) < class_la(CB) + class_lb(CB);
+}
+
+template <int CB, int CK, int OP, typename TV>
+void launch_lane_t(const CoopDev &cd, const SegLaunch &L) {
+  if (L.nq_hint == 0) return;
+  constexpr bool KL = lane_ket<CB, CK>();
+  using SH = LaneShape<CB, CK, KL>;
+  const int64_t blocks = (L.nq_hint > 0 && L.nq_hint < 256 * 32) ? L.nq_hint : 256 * 32;
+  hipLaunchKernelGGL((eri_lane_kernel<CB, CK, OP, KL, TV>), dim3((unsigned)blocks), dim3(64),
+                     SH::template lds_bytes<TV>(), L.stream, L.sys, L.nsys, L.seg, cd, L.list, L.nprim);
+}
+
+// HRR region the kernel reserves (doubles), for the host-side table check
+template <int CB, int CK>
+constexpr int lane_hrr_capacity() {
+  return 2 * LaneShape<CB, CK, lane_ket<CB, CK>()>::hrr_r();
+}
+
+}  // namespace hfx
+
+#define HFX_LANE_UNIT(CB, CK)                                                                        \
+  namespace hfx {                                                                                    \
+  void launch_eri_lane_r##CB##CK(int op, bool f32, const CoopDev &cd, const SegLaunch &L) {         \
+    if (f32) {                                                                                       \
+      if (op == 0)                                                                                   \
+        launch_lane_t<CB, CK, 0, float>(cd, L);                                                      \
+      else                                                                                           \
+        launch_lane_t<CB, CK, 1, float>(cd, L);                                                      \
+    } else {                                                                                         \
+      if (op == 0)                                                                                   \
+        launch_lane_t<CB, CK, 0, double>(cd, L);                                                     \
+      else                                                                                           \
+        launch_lane_t<CB, CK, 1, double>(cd, L);                                                     \
+    }                                                                                                \
+  }                                                                                                  \
+  int lane_hrr_capacity_r##CB##CK() { return lane_hrr_capacity<CB, CK>(); }                          \
+  }

@@ -148,11 +148,13 @@ struct hfx_plan_s {
   double *d_boys = nullptr;
   DevSys *d_sys1 = nullptr;  // device copy of ds (one-plan launches)
   bool schwarz_done = false;
-  // ---- cooperative (LDS) kernels for high angular-momentum classes
-  bool use_coop[kNQuartetClass] = {false};
+  // ---- ERI kernel per class: kern for the FP64 list, kern32 for the FP32
+  // list of mixed precision (a K_* variant); coop holds the op lists of the
+  // classes whose kernels take them (cooperative VRR, HRR of both)
+  int kern[kNQuartetClass] = {0};
+  int kern32[kNQuartetClass] = {0};
+  bool have_tables[kNQuartetClass] = {false};
   CoopDev coop[kNQuartetClass] = {};
-  // ---- FP32-list kernel per class: 0 FP32 register kernel, 1 the FP64 kernel
-  int fp32_kernel[kNQuartetClass] = {0};
   // ---- cached one-plan batch (hfx_build_K)
   struct Batch *self_batch = nullptr;
 };
@@ -474,6 +476,65 @@ hipError_t upload(hfx_plan_s &P, T **dst, const std::vector<T> &src) {
   return e;
 }
 
+// ERI kernel variants of a class
+enum { K_REG = 0, K_COOP = 1, K_LANE = 2, K_REG32 = 3, K_LANE32 = 4, K_NVARIANT = 5 };
+const char *const kKernName[K_NVARIANT] = {"reg", "coop", "lane", "reg32", "lane32"};
+
+bool variant_available(int cb, int ck, int v) {
+  switch (v) {
+    case K_REG:
+    case K_REG32: return register_available(cb, ck);
+    case K_COOP: return coop_available(cb, ck);
+    case K_LANE:
+    case K_LANE32: return lane_available(cb, ck);
+    default: return false;
+  }
+}
+bool variant_fp32(int v) { return v == K_REG32 || v == K_LANE32; }
+
+// FP32-list kernel that goes with FP64-list kernel k64
+int default_kern32(int cb, int ck, int k64) {
+  if (k64 == K_REG && variant_available(cb, ck, K_REG32)) return K_REG32;
+  if (k64 == K_LANE) return K_LANE32;
+  return k64;
+}
+
+// HFX_KERNELS="<cb><ck>=<name>,<cb><ck>/32=<name>,...": per-class kernel
+// choice for experiments (names as in kKernName)
+hfx_status apply_kernel_overrides(hfx_plan_s &P) {
+  const char *env = std::getenv("HFX_KERNELS");
+  if (!env) return HFX_OK;
+  std::string all(env);
+  size_t pos = 0;
+  while (pos < all.size()) {
+    size_t end = all.find(',', pos);
+    if (end == std::string::npos) end = all.size();
+    const std::string tok = all.substr(pos, end - pos);
+    pos = end + 1;
+    if (tok.empty()) continue;
+    const size_t eq = tok.find('=');
+    if (eq == std::string::npos || eq < 2 || tok[0] < '0' || tok[0] > '5' || tok[1] < '0' || tok[1] > tok[0])
+      return fail(HFX_ERR_INVALID, "HFX_KERNELS: bad entry " + tok);
+    const int cb = tok[0] - '0', ck = tok[1] - '0';
+    const bool f32 = tok.compare(2, eq - 2, "/32") == 0;
+    if (!f32 && eq != 2) return fail(HFX_ERR_INVALID, "HFX_KERNELS: bad entry " + tok);
+    const std::string name = tok.substr(eq + 1);
+    int v = -1;
+    for (int k = 0; k < K_NVARIANT; ++k)
+      if (name == kKernName[k]) v = k;
+    if (v < 0 || !variant_available(cb, ck, v) || (!f32 && variant_fp32(v)))
+      return fail(HFX_ERR_INVALID, "HFX_KERNELS: unavailable kernel in " + tok);
+    const int r = region_of(cb, ck);
+    if (f32) {
+      P.kern32[r] = v;
+    } else {
+      P.kern[r] = v;
+      P.kern32[r] = default_kern32(cb, ck, v);
+    }
+  }
+  return HFX_OK;
+}
+
 hfx_status upload_plan(hfx_plan_s &P) {
   HIPCHK(upload(P, &P.d_sh_xyz, P.sh_xyz));
   HIPCHK(upload(P, &P.d_sh_l, P.sh_l));
@@ -494,23 +555,20 @@ hfx_status upload_plan(hfx_plan_s &P) {
   HIPCHK(P.mem.alloc(&P.d_Dc, (size_t)P.nnz_c));
   HIPCHK(P.mem.alloc(&P.d_K4, (size_t)P.nnz_c));
   HIPCHK(upload(P, &P.d_boys, boys_table()));
-  // cooperative kernels: classes whose register-resident recursion would
-  // spill (d shells with total angular momentum >= 5)
-  const char *mask_env = std::getenv("HFX_COOP_MASK");
+  // op lists of the classes served by the cooperative or the lane kernel
   for (int cb = 0; cb < kNPairClass; ++cb)
     for (int ck = 0; ck <= cb; ++ck) {
       const int r = region_of(cb, ck);
       const int Lt = class_la(cb) + class_lb(cb) + class_la(ck) + class_lb(ck);
-      bool use = (cb >= 4 && Lt >= 6);
-      if (mask_env) use = ((std::strtoull(mask_env, nullptr, 0) >> r) & 1ull) != 0;
-      if (!register_available(cb, ck)) use = true;  // no one-lane kernel: always cooperative
-      if (!use || !coop_available(cb, ck)) continue;
+      if (!coop_available(cb, ck) && !lane_available(cb, ck)) continue;
       CoopHost h;
-      coop_build(cb, ck, 64 / coop_parallel(cb, ck), h);
+      coop_build(cb, ck, coop_available(cb, ck) ? 64 / coop_parallel(cb, ck) : 64, h);
       if (h.n_vrr_levels != Lt) return fail(HFX_ERR_DEVICE, "internal: cooperative level structure");
       for (int lv = 0; lv < h.n_vrr_levels; ++lv)
         if (h.levels[lv].y != coop_level_count(cb, ck, lv) || h.levels[lv].x != (lv ? h.levels[lv - 1].x + h.levels[lv - 1].y : 0))
           return fail(HFX_ERR_DEVICE, "internal: cooperative op list does not match the kernel shape");
+      if (lane_available(cb, ck) && (h.out_base + h.nout > lane_hrr_capacity(cb, ck) || h.nacc > lane_hrr_capacity(cb, ck)))
+        return fail(HFX_ERR_DEVICE, "internal: HRR workspace of the lane kernel too small");
       uint4 *d_ops = nullptr, *d_vops = nullptr;
       int4 *d_lv = nullptr;
       uint16_t *d_acc = nullptr;
@@ -533,10 +591,21 @@ hfx_status upload_plan(hfx_plan_s &P) {
       c.nb = ncart(h.lb);
       c.nc = ncart(h.lc);
       c.nd = ncart(h.ld);
-      P.use_coop[r] = true;
-      // mixed precision: FP32 one-lane kernel where it exists, else the FP64 cooperative one
-      P.fp32_kernel[r] = register_available(cb, ck) ? 0 : 1;
+      P.have_tables[r] = true;
     }
+  // default kernel per class, then any override from HFX_KERNELS
+  for (int cb = 0; cb < kNPairClass; ++cb)
+    for (int ck = 0; ck <= cb; ++ck) {
+      const int r = region_of(cb, ck);
+      // the lane kernel where the one-lane recursion spills or is absent
+      const bool light = (cb == 4 && ck == 1) || (cb == 5 && ck == 1);
+      P.kern[r] = (lane_available(cb, ck) && !light) ? K_LANE : K_REG;
+      P.kern32[r] = default_kern32(cb, ck, P.kern[r]);
+    }
+  {
+    hfx_status st = apply_kernel_overrides(P);
+    if (st != HFX_OK) return st;
+  }
 
   DevSys &s = P.ds;
   s.sh_xyz = P.d_sh_xyz;
@@ -786,6 +855,17 @@ namespace {
 std::mutex g_batch_mu;
 std::vector<Batch *> g_batches;  // multi-plan batches (one-plan batches live in their plan)
 
+void launch_variant(int v, int cb, int ck, int op, const CoopDev &cd, const SegLaunch &L) {
+  switch (v) {
+    case K_REG: launch_eri(cb, ck, op, L); break;
+    case K_COOP: launch_eri_coop(cb, ck, op, cd, L); break;
+    case K_LANE: launch_eri_lane(cb, ck, op, false, cd, L); break;
+    case K_REG32: launch_eri_f32(cb, ck, op, L); break;
+    case K_LANE32: launch_eri_lane(cb, ck, op, true, cd, L); break;
+    default: break;
+  }
+}
+
 hfx_status batch_init(Batch &B, const std::vector<hfx_plan_s *> &plans) {
   B.plans = plans;
   B.op = plans[0]->op;
@@ -908,19 +988,11 @@ hfx_status enqueue_build(Batch &B, const double *const *d_dev, double *const *k_
       if (evc) HIPCHK(hipEventRecord(evc[r], B.stream));
       SegLaunch L{B.d_sys, n, B.d_seg64 + so, B.d_list, B.d_nprim + r, -1, B.stream};
       if (!graph) L.nq_hint = B.h_seg64[so + n] - B.h_seg64[so];
-      if (P0.use_coop[r])
-        launch_eri_coop(cb, ck, B.op, P0.coop[r], L);
-      else
-        launch_eri(cb, ck, B.op, L);
+      launch_variant(P0.kern[r], cb, ck, B.op, P0.coop[r], L);
       if (B.mixed) {
         SegLaunch L32{B.d_sys, n, B.d_seg32 + so, B.d_list32, B.d_nprim + r, -1, B.stream};
         if (!graph) L32.nq_hint = B.h_seg32[so + n] - B.h_seg32[so];
-        if (P0.fp32_kernel[r] == 1 && P0.use_coop[r])
-          launch_eri_coop(cb, ck, B.op, P0.coop[r], L32);
-        else if (P0.fp32_kernel[r] == 1)
-          launch_eri(cb, ck, B.op, L32);
-        else
-          launch_eri_f32(cb, ck, B.op, L32);
+        launch_variant(P0.kern32[r], cb, ck, B.op, P0.coop[r], L32);
       }
       if (evc && r == 0) HIPCHK(hipEventRecord(evc[kNQuartetClass], B.stream));
     }
@@ -958,7 +1030,7 @@ void fill_info(Batch &B, hfx_build_info *info, hipEvent_t *ev, hipEvent_t *evc) 
       const int64_t q32 = B.mixed ? B.h_seg32[so + n] - B.h_seg32[so] : 0;
       info->n_quartets_class[r] = q64 + q32;
       info->n_quartets += q64 + q32;
-      if (P0.fp32_kernel[r] == 0) info->n_fp32_quartets += q32;
+      if (variant_fp32(P0.kern32[r])) info->n_fp32_quartets += q32;
       info->n_prim_quartets += (int64_t)np[r];
       double fp, fq;
       class_flops(class_la(cb), class_lb(cb), class_la(ck), class_lb(ck), B.op, fp, fq);

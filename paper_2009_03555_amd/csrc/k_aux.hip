@@ -60,6 +60,50 @@ void launch_eri_f32(int cb, int ck, int op, const SegLaunch &L) {
   table[region_of(cb, ck)](op, L);
 }
 
+#define HFX_DECL_LANE(CB, CK)                                                                          \
+  void launch_eri_lane_r##CB##CK(int op, bool f32, const CoopDev &cd, const SegLaunch &L);             \
+  int lane_hrr_capacity_r##CB##CK();
+HFX_DECL_LANE(4, 1)
+HFX_DECL_LANE(4, 2)
+HFX_DECL_LANE(4, 3)
+HFX_DECL_LANE(4, 4)
+HFX_DECL_LANE(5, 1)
+HFX_DECL_LANE(5, 2)
+HFX_DECL_LANE(5, 3)
+HFX_DECL_LANE(5, 4)
+HFX_DECL_LANE(5, 5)
+#undef HFX_DECL_LANE
+
+void launch_eri_lane(int cb, int ck, int op, bool f32, const CoopDev &cd, const SegLaunch &L) {
+  switch (cb * 10 + ck) {
+    case 41: launch_eri_lane_r41(op, f32, cd, L); break;
+    case 42: launch_eri_lane_r42(op, f32, cd, L); break;
+    case 43: launch_eri_lane_r43(op, f32, cd, L); break;
+    case 44: launch_eri_lane_r44(op, f32, cd, L); break;
+    case 51: launch_eri_lane_r51(op, f32, cd, L); break;
+    case 52: launch_eri_lane_r52(op, f32, cd, L); break;
+    case 53: launch_eri_lane_r53(op, f32, cd, L); break;
+    case 54: launch_eri_lane_r54(op, f32, cd, L); break;
+    case 55: launch_eri_lane_r55(op, f32, cd, L); break;
+    default: break;
+  }
+}
+
+int lane_hrr_capacity(int cb, int ck) {
+  switch (cb * 10 + ck) {
+    case 41: return lane_hrr_capacity_r41();
+    case 42: return lane_hrr_capacity_r42();
+    case 43: return lane_hrr_capacity_r43();
+    case 44: return lane_hrr_capacity_r44();
+    case 51: return lane_hrr_capacity_r51();
+    case 52: return lane_hrr_capacity_r52();
+    case 53: return lane_hrr_capacity_r53();
+    case 54: return lane_hrr_capacity_r54();
+    case 55: return lane_hrr_capacity_r55();
+    default: return 0;
+  }
+}
+
 void launch_schwarz(int cb, int op, const DevSys &s, int p0, int p1, hipStream_t st) {
   switch (cb) {
     case 0: launch_schwarz_c0(op, s, p0, p1, st); break;

@@ -247,3 +247,47 @@ def test_mixed_precision_cluster_config3_recipe():
     print(f"cluster5 mixed: {info['n_fp32_quartets']}/{info['n_quartets']} FP32, max|dK| {err:.2e}")
     assert info["n_fp32_quartets"] > 0
     assert err <= TOL_MIXED
+
+
+# ------------------------------------------------------ kernel variants
+# every ERI kernel variant of the d-shell classes against the oracle
+_VARIANTS = {
+    "lane": "41=lane,42=lane,43=lane,44=lane,51=lane,52=lane,53=lane,54=lane,55=lane",
+    "coop": "42=coop,43=coop,44=coop,51=coop,52=coop,53=coop,54=coop,55=coop",
+    "reg": "41=reg,42=reg,43=reg,51=reg",
+}
+
+
+@pytest.mark.parametrize("variant", sorted(_VARIANTS))
+def test_kernel_variants_match_oracle(variant, cell, monkeypatch):
+    monkeypatch.setenv("HFX_KERNELS", _VARIANTS[variant])
+    plan = hfx.Plan(cell.s)
+    Kd = torch.full_like(cell.Dd, np.nan)
+    info = plan.build_K(cell.Dd, Kd, flags=hfx.HFX_SYNC, info=True)
+    Kref, _ = cell.o.build_K()
+    err = np.max(np.abs(Kd.cpu().numpy() - Kref))
+    print(f"{variant}: max|dK| = {err:.3e}")
+    assert info["n_quartets"] == cell.info["n_quartets"]
+    assert err <= TOL_FP64
+
+
+@pytest.mark.parametrize("variant", ["lane", "coop"])
+def test_kernel_variants_mixed(variant, monkeypatch):
+    monkeypatch.setenv("HFX_KERNELS", _VARIANTS[variant])
+    s64 = _tiny_cell(seed=91)
+    smx = s64.with_(precision="mixed", fp32_cutoff=1e-4)
+    _, D, K64, _ = _build(s64)
+    _, _, Kmx, imx = _build(smx, D)
+    o = oracle.Oracle(s64)
+    o.set_density(D)
+    Kref, _ = o.build_K()
+    err = np.max(np.abs(Kmx - Kref))
+    print(f"{variant} mixed: {imx['n_fp32_quartets']}/{imx['n_quartets']} FP32, max|dK| {err:.2e}")
+    assert err <= TOL_MIXED
+    assert np.max(np.abs(K64 - Kref)) <= TOL_FP64
+
+
+def test_kernel_override_rejects_unavailable(monkeypatch):
+    monkeypatch.setenv("HFX_KERNELS", "55=reg")
+    with pytest.raises(hfx.HfxError):
+        hfx.Plan(_tiny_cell())
