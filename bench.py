@@ -93,13 +93,37 @@ def _cpu_model():
     return "unknown"
 
 
+def _build_series(plan, Dd, Kd, steps, warmup, label):
+    """warmup + timed builds of one plan; returns (latencies s, infos, total s)"""
+    import torch
+    from paper_2009_03555_amd import hfx
+    for w in range(warmup):
+        t = time.perf_counter()
+        plan.build_K(Dd, Kd, flags=hfx.HFX_SYNC)
+        print(f"# {label} warmup {w}: {time.perf_counter() - t:.2f} s", file=sys.stderr, flush=True)
+    torch.cuda.synchronize()
+    lat, infos = [], []
+    t0 = time.perf_counter()
+    for k in range(steps):
+        t = time.perf_counter()
+        info = plan.build_K(Dd, Kd, flags=hfx.HFX_TIMING, info=True)
+        torch.cuda.synchronize()
+        lat.append(time.perf_counter() - t)
+        infos.append(info)
+        print(f"# {label} step {k}: {lat[-1]:.3f} s, {info['n_quartets']} quartets", file=sys.stderr, flush=True)
+    torch.cuda.synchronize()
+    return lat, infos, time.perf_counter() - t0
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=2)
+    ap.add_argument("--steps", type=int, default=1)
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--workload", default="config2")
-    ap.add_argument("--precision", default="fp64", choices=["fp64", "mixed"])
+    ap.add_argument("--precision", default="both", choices=["fp64", "mixed", "both"],
+                    help="fp64: the plain form only; both: also the mixed-precision form, its "
+                         "throughput and max|dK| against the FP64 build")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     args = ap.parse_args()
@@ -117,7 +141,8 @@ def main():
         raise SystemExit("bench.py needs a HIP device")
     import systems
 
-    s = workload(args.workload, args.precision)
+    prec = "fp64" if args.precision in ("fp64", "both") else "mixed"
+    s = workload(args.workload, prec)
     plan = hfx.Plan(s)
     D = np.concatenate([v.ravel() for v in systems.density_blocks(s, plan.blocks.astype(np.int64))])
     Dd = torch.from_numpy(D).cuda()
@@ -126,24 +151,7 @@ def main():
     torch.cuda.synchronize()
     print(f"# {s.name}: {s.n_atoms} atoms, {s.n_shells} shells, {plan.n_blocks} blocks, nnz {plan.nnz}",
           file=sys.stderr, flush=True)
-    for w in range(args.warmup):
-        t = time.perf_counter()
-        plan.build_K(Dd, Kd, flags=hfx.HFX_SYNC)
-        print(f"# warmup {w}: {time.perf_counter() - t:.2f} s", file=sys.stderr, flush=True)
-
-    torch.cuda.synchronize()
-    lat = []
-    infos = []
-    t0 = time.perf_counter()
-    for k in range(args.steps):
-        t = time.perf_counter()
-        info = plan.build_K(Dd, Kd, flags=hfx.HFX_TIMING, info=True)
-        torch.cuda.synchronize()
-        lat.append(time.perf_counter() - t)
-        infos.append(info)
-        print(f"# step {k}: {lat[-1]:.3f} s, {info['n_quartets']} quartets", file=sys.stderr, flush=True)
-    torch.cuda.synchronize()
-    total = time.perf_counter() - t0
+    lat, infos, total = _build_series(plan, Dd, Kd, args.steps, args.warmup, prec)
 
     nq = infos[-1]["n_quartets"]
     value = nq * args.steps / total
@@ -174,11 +182,11 @@ def main():
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "f64" if args.precision == "fp64" else "f64+f32",
+        "dtype": "f64" if prec == "fp64" else "f32+f64",
         "data": "synthetic",
         "config": {"workload": s.name, "n_atoms": s.n_atoms, "n_shells": s.n_shells,
                    "n_basis": s.n_functions(), "periodic": s.periodic, "op": s.op, "omega": s.omega,
-                   "pair_cutoff": s.pair_cutoff, "tau": s.tau, "precision": args.precision,
+                   "pair_cutoff": s.pair_cutoff, "tau": s.tau, "precision": prec,
                    "n_blocks": plan.n_blocks, "nnz": plan.nnz},
         "builds_per_s": args.steps / total,
         "latency_ms_p50": float(np.percentile(lat, 50) * 1e3),
@@ -196,6 +204,28 @@ def main():
                     for r in range(21) if infos[-1]["n_quartets_class"][r]},
         "cpu_baseline": None,
     }
+    if args.precision == "both":
+        K64 = Kd.clone()
+        smx = s.with_(precision="mixed", fp32_cutoff=1e-6, name=s.name)
+        pmx = hfx.Plan(smx)
+        Kmx = torch.zeros_like(Dd)
+        pmx.schwarz()
+        lat_m, inf_m, tot_m = _build_series(pmx, Dd, Kmx, args.steps, args.warmup, "mixed")
+        err = float(torch.max(torch.abs(Kmx - K64)).item())
+        out["mixed"] = {
+            "fp32_cutoff": smx.fp32_cutoff,
+            "quartets_per_s": inf_m[-1]["n_quartets"] * args.steps / tot_m,
+            "builds_per_s": args.steps / tot_m,
+            "latency_ms_p50": float(np.percentile(lat_m, 50) * 1e3),
+            "latency_ms_p99": float(np.percentile(lat_m, 99) * 1e3),
+            "fp32_quartets": inf_m[-1]["n_fp32_quartets"],
+            "quartets_per_build": inf_m[-1]["n_quartets"],
+            "max_abs_dK_vs_fp64": err,
+            "speedup_vs_fp64": (args.steps / tot_m) / (args.steps / total),
+            "phase_ms": {k: float(np.mean([i[k] for i in inf_m])) for k in
+                         ("ms_density", "ms_screen", "ms_eri", "ms_finalize", "ms_total")},
+        }
+        pmx.destroy()
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(s, args.cpu_seconds)
     print(json.dumps(out))
