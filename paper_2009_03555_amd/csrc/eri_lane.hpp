@@ -21,6 +21,10 @@
 #include "eri_wave.hpp"
 #include "launchers.hpp"
 
+#ifndef HFX_LANE_WAVES
+#define HFX_LANE_WAVES 1
+#endif
+
 namespace hfx {
 
 template <int CB, int CK, bool KL>
@@ -60,23 +64,36 @@ struct LaneShape {
     for (int d = 1; d <= LD; ++d) r = cmax(r, NA * NB * (noff(FK - d + 1) - noff(LC)) * ncart(d));
     return r;
   }
-  template <typename TV>
+  // LDS exchange (XCH = 0) needs the publish buffers; register shuffles
+  // (XCH = 1) only the HRR region
+  template <typename TV, int XCH>
   __host__ __device__ static constexpr int work_doubles() {
-    return cmax(2 * hrr_r(), (2 * pbl() * 64 * (int)sizeof(TV) + 7) / 8);
+    return XCH == 0 ? cmax(2 * hrr_r(), (2 * pbl() * 64 * (int)sizeof(TV) + 7) / 8) : 2 * hrr_r();
   }
-  template <typename TV>
+  template <typename TV, int XCH>
   __host__ __device__ static constexpr size_t lds_bytes() {
-    return (size_t)(work_doubles<TV>() + NBATCH * kCoopStage) * sizeof(double);
+    return (size_t)(work_doubles<TV, XCH>() + NBATCH * kCoopStage) * sizeof(double);
   }
 };
+
+// LDS ordering between the lanes of the one wave of a work-group: a wave's
+// LDS operations complete in issue order, so a wavefront-scope fence (no
+// wait) and a compiler barrier suffice
+__device__ __forceinline__ void wave_lds_sync() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
 
 template <typename TV>
 __device__ __forceinline__ TV sel3v(int d, TV x, TV y, TV z) {
   return d == 0 ? x : (d == 1 ? y : z);
 }
 
-template <int CB, int CK, int OP, bool KL, typename TV>
-__global__ __launch_bounds__(64) void eri_lane_kernel(const DevSys *__restrict__ sys, int nsys,
+// XCH: how the electron-coupling operand crosses lanes: each level is
+// published to LDS and read back (0; register shuffles, 1, measured slower)
+template <int CB, int CK, int OP, bool KL, typename TV, int XCH>
+__global__ __launch_bounds__(64, HFX_LANE_WAVES) void eri_lane_kernel(const DevSys *__restrict__ sys, int nsys,
                                                       const int64_t *__restrict__ seg, CoopDev cd,
                                                       const uint64_t *__restrict__ list,
                                                       unsigned long long *__restrict__ nprim) {
@@ -88,7 +105,7 @@ __global__ __launch_bounds__(64) void eri_lane_kernel(const DevSys *__restrict__
   constexpr int XG = KL ? 9 : 15, YG = KL ? 12 : 18, OG2 = KL ? 21 : 23, RG = KL ? 22 : 24;
   extern __shared__ double W[];
   TV *pub = reinterpret_cast<TV *>(W);
-  double *stage = W + SH::template work_doubles<TV>();
+  double *stage = W + SH::template work_doubles<TV, XCH>();
   const int lane = threadIdx.x;
   const bool active = lane < NGRP * NS;
   const int grp = active ? lane / NS : 0;
@@ -105,24 +122,28 @@ __global__ __launch_bounds__(64) void eri_lane_kernel(const DevSys *__restrict__
     npow[i] = (TV)n;
     src[i] = n > 0 ? grp * NS + noff(ns - 1) + cidx(sub1(sc, i)) : lane;
   }
-  // ancestor chain of s: step k builds level k from level k-1 in direction
-  // cdir[k-1]; cpow[k-1] is the parent's power in that direction
-  int cdir[LS > 0 ? LS : 1];
-  TV cpow[LS > 0 ? LS : 1];
-  {
-    C3 cur = sc;
+  // ancestor chain of s, shifted so that every lane ends at step LS: lane
+  // level j = k - (LS - ns) is built at step k; earlier steps are identities
+  // (X = 1, Y = 0, no second term), which keep [0]^(m) with the m range every
+  // step needs (m <= L - k for all lanes).  xo/yo: stage slots of X and Y,
+  // cpw: the parent's power in the build direction.
+  int xo[LS > 0 ? LS : 1], yo[LS > 0 ? LS : 1];
+  TV cpw[LS > 0 ? LS : 1];
 #pragma unroll
-    for (int k = LS; k >= 1; --k) {
-      int d = 0, np = 0;
-      if (k <= ns) {
-        d = dir_of(cur);
-        const C3 par = sub1(cur, d);
-        np = pw(par, d);
-        cur = par;
-      }
-      cdir[k - 1] = d;
-      cpow[k - 1] = (TV)np;
+  for (int k = 1; k <= LS; ++k) {
+    const int j = k - (LS - ns);
+    C3 cur = sc;  // walk down to the ancestor at level j
+#pragma unroll
+    for (int t = 0; t < LS; ++t)
+      if (t < ns - j) cur = sub1(cur, dir_of(cur));
+    int d = 0, np = 0;
+    if (j >= 1) {
+      d = dir_of(cur);
+      np = pw(sub1(cur, d), d);
     }
+    xo[k - 1] = j >= 1 ? XS + d : 26;
+    yo[k - 1] = j >= 1 ? YS + d : 27;
+    cpw[k - 1] = (TV)np;
   }
 
   unsigned long long prims = 0;
@@ -168,19 +189,16 @@ __global__ __launch_bounds__(64) void eri_lane_kernel(const DevSys *__restrict__
         const TV xc[3] = {npow[0] * o2ze, npow[1] * o2ze, npow[2] * o2ze};
 
         // ---- lane side: [s, 0]^(m), m = 0..LG, along the ancestor chain
-        TV cur[L + 1], prv[L + 1], res[LG + 1];
+        TV cur[L + 1], prv[L + 1];
 #pragma unroll
         for (int m = 0; m <= L; ++m) cur[m] = live ? (TV)st[m] : (TV)0;
 #pragma unroll
         for (int m = 0; m <= L; ++m) prv[m] = (TV)0;
-#pragma unroll
-        for (int m = 0; m <= LG; ++m) res[m] = cur[m];
         sfor<1, LS + 1>([&](auto k_) {
           constexpr int k = decltype(k_)::value;
           constexpr int MK = L - k;
-          const int d = cdir[k - 1];
-          const TV X = sel3v(d, sx0, sx1, sx2), Y = sel3v(d, sy0, sy1, sy2);
-          const TV cn = cpow[k - 1] * o2s;
+          const TV X = (TV)st[xo[k - 1]], Y = (TV)st[yo[k - 1]];
+          const TV cn = cpw[k - 1] * o2s;
           TV nw[MK + 1];
 #pragma unroll
           for (int m = 0; m <= MK; ++m) {
@@ -188,9 +206,6 @@ __global__ __launch_bounds__(64) void eri_lane_kernel(const DevSys *__restrict__
             if constexpr (k >= 2) v = fma(cn, fma(-rs, prv[m + 1], prv[m]), v);
             nw[m] = v;
           }
-          const bool take = (k == ns);
-#pragma unroll
-          for (int m = 0; m <= LG; ++m) res[m] = take ? nw[m] : res[m];
 #pragma unroll
           for (int m = 0; m <= MK + 1; ++m) prv[m] = cur[m];
 #pragma unroll
@@ -200,12 +215,12 @@ __global__ __launch_bounds__(64) void eri_lane_kernel(const DevSys *__restrict__
         // ---- grow side in registers, electron coupling through LDS
         TV V[SH::NV];
 #pragma unroll
-        for (int m = 0; m <= LG; ++m) V[SH::vo(0, 0, m)] = res[m];
+        for (int m = 0; m <= LG; ++m) V[SH::vo(0, 0, m)] = cur[m];
         if constexpr (GL == 0) acc[0] += V[0];
-        if constexpr (LG > 0) {
+        if constexpr (XCH == 0 && LG > 0) {
 #pragma unroll
           for (int m = 1; m <= LG; ++m) pub[(m - 1) * 64 + lane] = V[SH::vo(0, 0, m)];
-          __syncthreads();
+          wave_lds_sync();
         }
         sfor<1, LG + 1>([&](auto lv_) {
           constexpr int lv = decltype(lv_)::value;
@@ -221,7 +236,12 @@ __global__ __launch_bounds__(64) void eri_lane_kernel(const DevSys *__restrict__
             constexpr int ppc = np > 0 ? cidx(sub1(p, i)) : 0;
             TV R[MR + 1];
 #pragma unroll
-            for (int m = 0; m <= MR; ++m) R[m] = pub[(rb + pc * (MR + 1) + m) * 64 + src[i]];
+            for (int m = 0; m <= MR; ++m) {
+              if constexpr (XCH == 0)
+                R[m] = pub[(rb + pc * (MR + 1) + m) * 64 + src[i]];
+              else
+                R[m] = __shfl(V[SH::vo(lv - 1, pc, m + 1)], src[i]);
+            }
 #pragma unroll
             for (int m = 0; m <= MR; ++m) {
               TV v = fma(gY[i], V[SH::vo(lv - 1, pc, m + 1)], gX[i] * V[SH::vo(lv - 1, pc, m)]);
@@ -231,13 +251,13 @@ __global__ __launch_bounds__(64) void eri_lane_kernel(const DevSys *__restrict__
             }
             if constexpr (lv >= GL) acc[noff(lv) + c - noff(GL)] += V[SH::vo(lv, c, 0)];
           });
-          if constexpr (lv < LG) {
+          if constexpr (XCH == 0 && lv < LG) {
             sfor<0, ncart(lv)>([&](auto c_) {
               constexpr int c = decltype(c_)::value;
 #pragma unroll
               for (int m = 1; m <= MR; ++m) pub[(wb + c * MR + m - 1) * 64 + lane] = V[SH::vo(lv, c, m)];
             });
-            __syncthreads();
+            wave_lds_sync();
           }
         });
       }
@@ -277,8 +297,9 @@ void launch_lane_t(const CoopDev &cd, const SegLaunch &L) {
   constexpr bool KL = lane_ket<CB, CK>();
   using SH = LaneShape<CB, CK, KL>;
   const int64_t blocks = (L.nq_hint > 0 && L.nq_hint < 256 * 32) ? L.nq_hint : 256 * 32;
-  hipLaunchKernelGGL((eri_lane_kernel<CB, CK, OP, KL, TV>), dim3((unsigned)blocks), dim3(64),
-                     SH::template lds_bytes<TV>(), L.stream, L.sys, L.nsys, L.seg, cd, L.list, L.nprim);
+  constexpr size_t lds = SH::template lds_bytes<TV, 0>();
+  hipLaunchKernelGGL((eri_lane_kernel<CB, CK, OP, KL, TV, 0>), dim3((unsigned)blocks), dim3(64), lds, L.stream,
+                     L.sys, L.nsys, L.seg, cd, L.list, L.nprim);
 }
 
 // HRR region the kernel reserves (doubles), for the host-side table check

@@ -30,8 +30,9 @@ __device__ __forceinline__ double lds(const char *base, uint32_t byte_off) {
 //   9..11    P - A        12..14  W - P
 //   15..17   Q - C        18..20  W - Q
 //   21 1/(2 zeta)  22 rho/zeta  23 1/(2 eta)  24 rho/eta  25 1/(2 (zeta + eta))
+//   26 1.0  27 0.0 (coefficients of an identity step)
 constexpr int kCoopBatch = 16;  // batch of the cooperative kernel
-constexpr int kCoopStage = 26;
+constexpr int kCoopStage = 28;
 
 // lanes 0 .. nbatch-1 stage primitive quartets t0 .. t0+nbatch-1 (those < n)
 template <int L, int OP>
@@ -61,6 +62,7 @@ __device__ __forceinline__ void stage_prims(double *stage, int lane, int nbatch,
     st[15] = k[4]; st[16] = k[5]; st[17] = k[6];
     st[18] = fz * PQx; st[19] = fz * PQy; st[20] = fz * PQz;
     st[21] = 0.5 / zeta; st[22] = rho / zeta; st[23] = 0.5 / eta; st[24] = rho / eta; st[25] = 0.5 * ize;
+    st[26] = 1.0; st[27] = 0.0;
   }
 }
 

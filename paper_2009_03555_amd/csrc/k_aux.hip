@@ -2,6 +2,8 @@
 // P_max (Eq. dmscreening), quartet screening and compaction (Eq. schwarz
 // times P_scr, 8-fold unique enumeration), K finalisation, fills.
 
+#include <cstdlib>
+
 #include "coop.hpp"
 #include "launchers.hpp"
 
