@@ -160,6 +160,39 @@ hfx_status hfx_build_K(hfx_plan_t plan, const double *d_dev, double *k_dev, uint
 hfx_status hfx_build_K_multi(int32_t n, const hfx_plan_t *plans, const double *const *d_dev,
                              double *const *k_dev, uint32_t flags, hfx_build_info *info);
 
+/* Screened quartet count of a build with density d_dev, without building:
+ * density transform, P_max and the counting pass of the screening only.
+ * n64: quartets of the FP64 list, n32: of the FP32 list (mixed precision,
+ * else 0); the quartet lists of a build need 8 bytes per quartet.  For
+ * admission control before the first build. */
+hfx_status hfx_screen_count(hfx_plan_t plan, const double *d_dev, int64_t *n64, int64_t *n32);
+
+/* Autotuner (project-written): for every quartet class of the plan's
+ * current screened list, time each available ERI kernel variant (one-lane
+ * register recursion, wave-cooperative LDS recursion, lane-per-component
+ * recursion; for the FP32 list of mixed precision also their FP32 forms) at
+ * several grid sizes on the first max_quartets quartets of the class (all if
+ * <= 0), keep the fastest for later builds of this plan (and of fused
+ * multi-plan builds it leads), then run one build into k_dev.  Costs roughly
+ * two builds of the sampled prefixes.  report may be NULL. */
+#define HFX_TUNE_MAX_CAND 12
+typedef struct {
+  int32_t variant; /* 0 register, 1 cooperative, 2 lane, 3 register FP32, 4 lane FP32 */
+  int32_t fp32_list; /* 1: candidate for the FP32 list of mixed precision */
+  int64_t max_blocks; /* grid cap of the candidate (0: the kernel's default) */
+  double ms;          /* time of the sampled prefix */
+} hfx_tune_candidate;
+typedef struct {
+  int32_t n_candidates[HFX_N_CLASSES];
+  int64_t sample_quartets[HFX_N_CLASSES];    /* FP64 list prefix timed */
+  int64_t sample_quartets32[HFX_N_CLASSES];  /* FP32 list prefix timed */
+  int32_t chosen[HFX_N_CLASSES];    /* index into cand of the FP64-list choice, -1 if none timed */
+  int32_t chosen32[HFX_N_CLASSES];  /* same for the FP32 list */
+  hfx_tune_candidate cand[HFX_N_CLASSES][HFX_TUNE_MAX_CAND];
+} hfx_tune_report;
+hfx_status hfx_autotune(hfx_plan_t plan, const double *d_dev, double *k_dev, int64_t max_quartets,
+                        hfx_tune_report *report);
+
 /* Host copies of the last hfx_build_K's screening data, for verification:
  * what = 0: P_max per pattern block (n doubles, n = n_blocks);
  * what = 1: quartet list as uint64 (bra pair | ket pair << 24 | image << 48),

@@ -194,7 +194,7 @@ template <int CB, int CK, int OP>
 void launch_coop_t(const CoopDev &cd, const SegLaunch &L) {
   if (L.nq_hint == 0) return;
   constexpr int P = coop_parallel(CB, CK);
-  const int64_t blocks = (L.nq_hint > 0 && L.nq_hint < 256 * 32) ? L.nq_hint : 256 * 32;
+  const int64_t blocks = seg_grid(L, L.nq_hint, 256 * 32);
   const size_t lds = ((size_t)P * (cd.nw + 1) + (size_t)kCoopBatch * kCoopStage) * sizeof(double);
   hipLaunchKernelGGL((eri_coop_kernel<CB, CK, OP, P, 0>), dim3((unsigned)blocks), dim3(64), lds, L.stream, L.sys,
                      L.nsys, L.seg, cd, L.list, L.nprim, 0, (int64_t)0);

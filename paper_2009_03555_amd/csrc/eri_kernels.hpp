@@ -196,8 +196,10 @@ template <int CB, int CK, int OP, typename TV = double>
 void launch_eri_t(const SegLaunch &L) {
   if (L.nq_hint == 0) return;
   const int threads = 256;
-  int64_t blocks = L.nq_hint > 0 ? (L.nq_hint + threads - 1) / threads : 256 * 8;
-  if (blocks > 256 * 64) blocks = 256 * 64;
+  // known count: one thread per quartet up to 256 * 64 blocks; graph
+  // replays (count unknown on the host): 256 * 8 blocks that stride
+  const int64_t need = L.nq_hint > 0 ? (L.nq_hint + threads - 1) / threads : -1;
+  const int64_t blocks = seg_grid(L, need, need > 0 ? 256 * 64 : 256 * 8);
   hipLaunchKernelGGL((eri_digest_kernel<CB, CK, OP, TV>), dim3((unsigned)blocks), dim3(threads), 0, L.stream,
                      L.sys, L.nsys, L.seg, L.list, L.nprim);
 }

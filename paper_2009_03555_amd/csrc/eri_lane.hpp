@@ -296,7 +296,7 @@ void launch_lane_t(const CoopDev &cd, const SegLaunch &L) {
   if (L.nq_hint == 0) return;
   constexpr bool KL = lane_ket<CB, CK>();
   using SH = LaneShape<CB, CK, KL>;
-  const int64_t blocks = (L.nq_hint > 0 && L.nq_hint < 256 * 32) ? L.nq_hint : 256 * 32;
+  const int64_t blocks = seg_grid(L, L.nq_hint, 256 * 32);
   constexpr size_t lds = SH::template lds_bytes<TV, 0>();
   hipLaunchKernelGGL((eri_lane_kernel<CB, CK, OP, KL, TV, 0>), dim3((unsigned)blocks), dim3(64), lds, L.stream,
                      L.sys, L.nsys, L.seg, cd, L.list, L.nprim);

@@ -153,6 +153,8 @@ struct hfx_plan_s {
   // classes whose kernels take them (cooperative VRR, HRR of both)
   int kern[kNQuartetClass] = {0};
   int kern32[kNQuartetClass] = {0};
+  int64_t grid[kNQuartetClass] = {0};    // grid caps (0: the kernel's default)
+  int64_t grid32[kNQuartetClass] = {0};
   bool have_tables[kNQuartetClass] = {false};
   CoopDev coop[kNQuartetClass] = {};
   // ---- cached one-plan batch (hfx_build_K)
@@ -986,11 +988,11 @@ hfx_status enqueue_build(Batch &B, const double *const *d_dev, double *const *k_
       const int r = region_of(cb, ck);
       const size_t so = (size_t)r * (n + 1);
       if (evc) HIPCHK(hipEventRecord(evc[r], B.stream));
-      SegLaunch L{B.d_sys, n, B.d_seg64 + so, B.d_list, B.d_nprim + r, -1, B.stream};
+      SegLaunch L{B.d_sys, n, B.d_seg64 + so, B.d_list, B.d_nprim + r, -1, B.stream, P0.grid[r]};
       if (!graph) L.nq_hint = B.h_seg64[so + n] - B.h_seg64[so];
       launch_variant(P0.kern[r], cb, ck, B.op, P0.coop[r], L);
       if (B.mixed) {
-        SegLaunch L32{B.d_sys, n, B.d_seg32 + so, B.d_list32, B.d_nprim + r, -1, B.stream};
+        SegLaunch L32{B.d_sys, n, B.d_seg32 + so, B.d_list32, B.d_nprim + r, -1, B.stream, P0.grid32[r]};
         if (!graph) L32.nq_hint = B.h_seg32[so + n] - B.h_seg32[so];
         launch_variant(P0.kern32[r], cb, ck, B.op, P0.coop[r], L32);
       }
@@ -1139,6 +1141,89 @@ hfx_status run_batch(Batch &B, const double *const *d_dev, double *const *k_dev,
   return st;
 }
 
+// graphs of every batch that contains P (its kernel choice has changed)
+void drop_graphs_of(const hfx_plan_s *P) {
+  if (P->self_batch) drop_graph(*P->self_batch);
+  std::lock_guard<std::mutex> lk(g_batch_mu);
+  for (Batch *B : g_batches)
+    if (std::find(B->plans.begin(), B->plans.end(), P) != B->plans.end()) drop_graph(*B);
+}
+
+// grid caps tried per kernel family (0 = default)
+const int64_t kTuneGridReg[] = {0, 256 * 4, 256 * 16};
+const int64_t kTuneGridWave[] = {0, 256 * 8, 256 * 64};
+
+hfx_status tune_class(Batch &B, int cb, int ck, bool f32, int64_t max_q, int64_t *d_seg2, hfx_tune_report *rep) {
+  hfx_plan_s &P = *B.plans[0];
+  const int r = region_of(cb, ck);
+  const std::vector<int64_t> &hs = f32 ? B.h_seg32 : B.h_seg64;
+  const int64_t s0 = hs[(size_t)r * 2], s1 = hs[(size_t)r * 2 + 1];
+  const int64_t nq = s1 - s0;
+  if (nq <= 0) return HFX_OK;
+  const int64_t take = (max_q > 0 && max_q < nq) ? max_q : nq;
+  const int64_t seg2[2] = {s0, s0 + take};
+  HIPCHK(hipMemcpyAsync(d_seg2, seg2, sizeof(seg2), hipMemcpyHostToDevice, B.stream));
+  std::vector<std::pair<int, int64_t>> cands;
+  const int vars64[] = {K_REG, K_COOP, K_LANE};
+  const int vars32[] = {K_REG32, K_LANE32, K_REG, K_COOP, K_LANE};
+  const int *vars = f32 ? vars32 : vars64;
+  const int nv = f32 ? 5 : 3;
+  for (int k = 0; k < nv; ++k) {
+    const int v = vars[k];
+    if (!variant_available(cb, ck, v)) continue;
+    const bool wave = (v == K_COOP || v == K_LANE || v == K_LANE32);
+    for (int64_t g : (wave ? kTuneGridWave : kTuneGridReg))
+      if ((int)cands.size() < HFX_TUNE_MAX_CAND) cands.emplace_back(v, g);
+  }
+  if (cands.empty()) return HFX_OK;
+  hipEvent_t e0, e1;
+  HIPCHK(hipEventCreate(&e0));
+  HIPCHK(hipEventCreate(&e1));
+  std::vector<float> ms(cands.size(), 0.0f);
+  for (size_t c = 0; c < cands.size(); ++c) {
+    SegLaunch L{B.d_sys, 1, d_seg2, f32 ? B.d_list32 : B.d_list, B.d_nprim + r, take, B.stream, cands[c].second};
+    // first run loads the code object and warms the caches; the second is timed
+    launch_variant(cands[c].first, cb, ck, B.op, P.coop[r], L);
+    (void)hipEventRecord(e0, B.stream);
+    launch_variant(cands[c].first, cb, ck, B.op, P.coop[r], L);
+    (void)hipEventRecord(e1, B.stream);
+    hipError_t e = hipEventSynchronize(e1);
+    if (e == hipSuccess) e = hipGetLastError();
+    if (e != hipSuccess) {
+      (void)hipEventDestroy(e0);
+      (void)hipEventDestroy(e1);
+      return fail(HFX_ERR_DEVICE, std::string("autotune: ") + hipGetErrorString(e));
+    }
+    (void)hipEventElapsedTime(&ms[c], e0, e1);
+  }
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  size_t best = 0;
+  for (size_t c = 1; c < cands.size(); ++c)
+    if (ms[c] < ms[best]) best = c;
+  if (f32) {
+    P.kern32[r] = cands[best].first;
+    P.grid32[r] = cands[best].second;
+  } else {
+    P.kern[r] = cands[best].first;
+    P.grid[r] = cands[best].second;
+  }
+  if (rep) {
+    int base = rep->n_candidates[r];
+    for (size_t c = 0; c < cands.size() && base < HFX_TUNE_MAX_CAND; ++c, ++base) {
+      hfx_tune_candidate &t = rep->cand[r][base];
+      t.variant = cands[c].first;
+      t.fp32_list = f32 ? 1 : 0;
+      t.max_blocks = cands[c].second;
+      t.ms = ms[c];
+      if (c == best) (f32 ? rep->chosen32[r] : rep->chosen[r]) = base;
+    }
+    rep->n_candidates[r] = base;
+    (f32 ? rep->sample_quartets32[r] : rep->sample_quartets[r]) = take;
+  }
+  return HFX_OK;
+}
+
 void drop_batches_of(const hfx_plan_s *P) {
   std::lock_guard<std::mutex> lk(g_batch_mu);
   for (size_t i = 0; i < g_batches.size();) {
@@ -1170,6 +1255,71 @@ hfx_status hfx_build_K(hfx_plan_t plan, const double *d_dev, double *k_dev, uint
     P.self_batch = B;
   }
   return run_batch(*P.self_batch, &d_dev, &k_dev, flags, info);
+}
+
+hfx_status hfx_screen_count(hfx_plan_t plan, const double *d_dev, int64_t *n64, int64_t *n32) {
+  if (!valid_plan(plan)) return fail(HFX_ERR_STATE, "invalid or destroyed plan");
+  if (!d_dev || !n64) return fail(HFX_ERR_INVALID, "NULL argument");
+  hfx_plan_s &P = *plan;
+  if (!P.schwarz_done) {
+    hfx_status st = run_schwarz(P);
+    if (st != HFX_OK) return st;
+  }
+  if (!P.self_batch) {
+    Batch *B = new Batch();
+    hfx_status st = batch_init(*B, {&P});
+    if (st != HFX_OK) {
+      delete B;
+      return st;
+    }
+    P.self_batch = B;
+  }
+  Batch &B = *P.self_batch;
+  launch_zero_u64(P.d_pglob, 1, B.stream);
+  launch_density(P.ds, (int64_t)P.blocks.size(), P.d_blk_IJ, P.d_blk_off, P.d_partner, P.d_canon, P.sph, d_dev, P.d_Dc,
+                 B.stream);
+  launch_zero_i32(B.d_err, 2, B.stream);
+  int64_t tot[2] = {0, 0};
+  for (int pass = 0; pass < (B.mixed ? 2 : 1); ++pass) {
+    const int mode = B.mixed ? 1 + pass : 0;
+    launch_screen(B.d_sys, B.d_items, B.nitems, B.d_counts, B.d_offsets, nullptr, 0, B.d_err, false, mode, B.stream);
+    HIPCHK(scan_counts(B.d_counts, B.d_offsets, B.nitems, B.d_scan_tmp, B.stream));
+    HIPCHK(hipMemcpyAsync(&tot[pass], B.d_offsets + B.nitems, sizeof(int64_t), hipMemcpyDeviceToHost, B.stream));
+  }
+  HIPCHK(hipStreamSynchronize(B.stream));
+  hfx_status st = check_err(B, nullptr);
+  if (st != HFX_OK) return st;
+  *n64 = tot[0];
+  if (n32) *n32 = tot[1];
+  return HFX_OK;
+}
+
+hfx_status hfx_autotune(hfx_plan_t plan, const double *d_dev, double *k_dev, int64_t max_quartets,
+                        hfx_tune_report *report) {
+  if (!valid_plan(plan)) return fail(HFX_ERR_STATE, "invalid or destroyed plan");
+  if (!d_dev || !k_dev) return fail(HFX_ERR_INVALID, "D or K pointer is NULL");
+  hfx_plan_s &P = *plan;
+  if (report) {
+    std::memset(report, 0, sizeof(*report));
+    for (int r = 0; r < kNQuartetClass; ++r) report->chosen[r] = report->chosen32[r] = -1;
+  }
+  // an eager build fills the lists the candidates are timed on
+  hfx_status st = hfx_build_K(plan, d_dev, k_dev, HFX_SYNC, nullptr);
+  if (st != HFX_OK) return st;
+  Batch &B = *P.self_batch;
+  int64_t *d_seg2 = nullptr;
+  HIPCHK(hipMalloc((void **)&d_seg2, 2 * sizeof(int64_t)));
+  for (int cb = 0; cb < kNPairClass && st == HFX_OK; ++cb)
+    for (int ck = 0; ck <= cb && st == HFX_OK; ++ck) {
+      st = tune_class(B, cb, ck, false, max_quartets, d_seg2, report);
+      if (st == HFX_OK && B.mixed) st = tune_class(B, cb, ck, true, max_quartets, d_seg2, report);
+    }
+  (void)hipStreamSynchronize(B.stream);
+  (void)hipFree(d_seg2);
+  if (st != HFX_OK) return st;
+  drop_graphs_of(&P);
+  // the timed launches accumulated into K4: one clean build with the choices
+  return hfx_build_K(plan, d_dev, k_dev, HFX_SYNC, nullptr);
 }
 
 hfx_status hfx_build_K_multi(int32_t n, const hfx_plan_t *plans, const double *const *d_dev, double *const *k_dev,

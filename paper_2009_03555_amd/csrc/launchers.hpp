@@ -17,7 +17,13 @@ struct SegLaunch {
   unsigned long long *nprim;    // device counter of primitive quartets (this class)
   int64_t nq_hint;              // quartets if known on the host, -1 if not
   hipStream_t stream;
+  int64_t max_blocks = 0;       // grid cap (0: the launcher's default)
 };
+// grid of a launch: `need` blocks if known (> 0), capped at max_blocks or def
+inline int64_t seg_grid(const SegLaunch &L, int64_t need, int64_t def) {
+  const int64_t cap = L.max_blocks > 0 ? L.max_blocks : def;
+  return (need > 0 && need < cap) ? need : cap;
+}
 
 #define HFX_DECL_R(CB, CK)                                                                             \
   void launch_eri_r##CB##CK(int op, const SegLaunch &L);

@@ -68,6 +68,33 @@ class hfx_build_info(ctypes.Structure):
         return d
 
 
+TUNE_MAX_CAND = 12
+VARIANT_NAMES = ["reg", "coop", "lane", "reg32", "lane32"]
+
+
+class hfx_tune_candidate(ctypes.Structure):
+    _fields_ = [("variant", ctypes.c_int32), ("fp32_list", ctypes.c_int32), ("max_blocks", ctypes.c_int64),
+                ("ms", ctypes.c_double)]
+
+
+class hfx_tune_report(ctypes.Structure):
+    _fields_ = [("n_candidates", ctypes.c_int32 * N_CLASSES), ("sample_quartets", ctypes.c_int64 * N_CLASSES),
+                ("sample_quartets32", ctypes.c_int64 * N_CLASSES), ("chosen", ctypes.c_int32 * N_CLASSES),
+                ("chosen32", ctypes.c_int32 * N_CLASSES),
+                ("cand", (hfx_tune_candidate * TUNE_MAX_CAND) * N_CLASSES)]
+
+    def as_list(self):
+        """per class: {"candidates": [(variant, fp32_list, max_blocks, ms)], "chosen", "chosen32", samples}"""
+        out = []
+        for r in range(N_CLASSES):
+            c = [(VARIANT_NAMES[t.variant], bool(t.fp32_list), int(t.max_blocks), float(t.ms))
+                 for t in list(self.cand[r])[: self.n_candidates[r]]]
+            out.append({"candidates": c, "chosen": int(self.chosen[r]), "chosen32": int(self.chosen32[r]),
+                        "sample_quartets": int(self.sample_quartets[r]),
+                        "sample_quartets32": int(self.sample_quartets32[r])})
+        return out
+
+
 _lib = None
 
 
@@ -91,8 +118,10 @@ def lib():
                                         ctypes.POINTER(vp), ctypes.c_uint32, ctypes.POINTER(hfx_build_info)]
         L.hfx_export.argtypes = [vp, ctypes.c_int32, vp, ctypes.POINTER(ctypes.c_int64)]
         L.hfx_plan_destroy.argtypes = [vp]
+        L.hfx_autotune.argtypes = [vp, vp, vp, ctypes.c_int64, ctypes.POINTER(hfx_tune_report)]
+        L.hfx_screen_count.argtypes = [vp, vp, ctypes.POINTER(ctypes.c_int64), ctypes.POINTER(ctypes.c_int64)]
         for name in ("hfx_footprint", "hfx_plan", "hfx_pattern", "hfx_schwarz", "hfx_build_K",
-                     "hfx_build_K_multi", "hfx_export", "hfx_plan_destroy"):
+                     "hfx_build_K_multi", "hfx_export", "hfx_plan_destroy", "hfx_autotune", "hfx_screen_count"):
             getattr(L, name).restype = ctypes.c_int
         _lib = L
     return _lib
@@ -190,6 +219,21 @@ class Plan:
         _check(lib().hfx_build_K(self._h, ctypes.c_void_p(_ptr(D)), ctypes.c_void_p(_ptr(K)), ctypes.c_uint32(flags),
                                  ctypes.byref(inf) if inf is not None else None))
         return inf.as_dict() if inf is not None else None
+
+    def screen_count(self, D):
+        """``hfx_screen_count``: (FP64-list, FP32-list) quartet counts for density D."""
+        n64 = ctypes.c_int64(0)
+        n32 = ctypes.c_int64(0)
+        _check(lib().hfx_screen_count(self._h, ctypes.c_void_p(_ptr(D)), ctypes.byref(n64), ctypes.byref(n32)))
+        return int(n64.value), int(n32.value)
+
+    def autotune(self, D, K, max_quartets: int = 200_000):
+        """``hfx_autotune``: choose the ERI kernel variant and grid per class
+        by timing, then build K; returns the per-class report."""
+        rep = hfx_tune_report()
+        _check(lib().hfx_autotune(self._h, ctypes.c_void_p(_ptr(D)), ctypes.c_void_p(_ptr(K)),
+                                  ctypes.c_int64(max_quartets), ctypes.byref(rep)))
+        return rep.as_list()
 
     def export(self, what: int) -> np.ndarray:
         n = ctypes.c_int64(0)

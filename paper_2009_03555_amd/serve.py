@@ -1,0 +1,214 @@
+"""Continuous-batching server of exchange builds.
+
+Requests (a system, a number of SCF iterations, an arrival time) enter a
+FIFO queue.  The scheduler works in steps at the granularity of one SCF
+iteration (iteration-level batching): before each step it admits queued
+requests that have arrived, in arrival order, as long as their device
+footprint fits under the HBM limit; the step then runs one exchange build for
+every admitted request together (one fused ``hfx_build_K_multi`` launch
+sequence); requests that have done all their iterations retire and free their
+memory, so requests that arrived meanwhile join the next step.  Each admitted
+request keeps its plan (pairs, primitive pairs, Schwarz table), its densities
+and its K on the device for its whole lifetime.
+
+The paper's own scheme for this is the two-level master/worker distribution
+of quartet batches over MPI ranks (its Sec. on parallelisation); here one GPU
+serves many systems at once instead.
+
+The scheduler is independent of the device: an executor object provides
+``static_footprint(request) -> bytes`` (a host-only lower bound, used to
+reject requests that can never fit), ``footprint(request) -> bytes`` (the
+admission size, asked for the head of the queue only), ``admit(request) ->
+state``,
+``step(states)`` (one build for each state, at its current iteration) and
+``retire(state) -> result``.  ``HipExecutor`` is the device executor; tests
+drive the scheduler with a host-only executor and a virtual clock.
+"""
+from __future__ import annotations
+
+import dataclasses
+import time
+from typing import Any, Callable, List, Optional, Sequence
+
+import numpy as np
+
+
+@dataclasses.dataclass
+class ServeRequest:
+    rid: int
+    system: Any
+    n_iter: int = 10
+    arrival_s: float = 0.0
+
+
+@dataclasses.dataclass
+class ServeResult:
+    rid: int
+    arrival_s: float
+    admitted_s: float
+    finished_s: float
+    n_iter: int
+    steps: List[int]            # scheduler steps this request took part in
+    result: Any = None          # executor's result (e.g. the final K)
+
+    @property
+    def latency_s(self) -> float:
+        return self.finished_s - self.arrival_s
+
+
+@dataclasses.dataclass
+class ServeStats:
+    results: List[ServeResult]
+    wall_s: float
+    n_steps: int
+    builds: int
+    max_concurrent: int
+    peak_reserved_bytes: int
+
+    def latency_percentile(self, q: float) -> float:
+        return float(np.percentile([r.latency_s for r in self.results], q)) if self.results else 0.0
+
+    @property
+    def builds_per_s(self) -> float:
+        return self.builds / self.wall_s if self.wall_s > 0 else 0.0
+
+    def summary(self) -> dict:
+        return {"requests": len(self.results), "builds": self.builds, "steps": self.n_steps,
+                "wall_s": self.wall_s, "builds_per_s": self.builds_per_s,
+                "latency_ms_p50": self.latency_percentile(50) * 1e3,
+                "latency_ms_p99": self.latency_percentile(99) * 1e3,
+                "max_concurrent": self.max_concurrent, "peak_reserved_bytes": self.peak_reserved_bytes}
+
+
+class Server:
+    """Iteration-level continuous batching under an HBM budget."""
+
+    def __init__(self, executor, hbm_limit_bytes: int, max_batch: int = 64,
+                 clock: Optional[Callable[[], float]] = None, sleep: Optional[Callable[[float], None]] = None):
+        self.ex = executor
+        self.limit = int(hbm_limit_bytes)
+        self.max_batch = int(max_batch)
+        self.clock = clock or time.perf_counter
+        self.sleep = sleep or time.sleep
+
+    def run(self, requests: Sequence[ServeRequest]) -> ServeStats:
+        queue = sorted(requests, key=lambda r: (r.arrival_s, r.rid))
+        for r in queue:
+            if self.ex.static_footprint(r) > self.limit:
+                raise ValueError(f"request {r.rid} needs more device memory than the limit")
+        t0 = self.clock()
+        active = []          # [request, state, reserved bytes, iterations done, admitted time, steps]
+        results: List[ServeResult] = []
+        reserved = 0
+        peak = 0
+        n_steps = 0
+        builds = 0
+        max_conc = 0
+        qi = 0
+        while qi < len(queue) or active:
+            now = self.clock() - t0
+            # admit arrived requests in FIFO order while they fit
+            while (qi < len(queue) and queue[qi].arrival_s <= now and len(active) < self.max_batch):
+                need = self.ex.footprint(queue[qi])
+                if reserved + need > self.limit:
+                    break
+                st = self.ex.admit(queue[qi])
+                reserved += need
+                peak = max(peak, reserved)
+                active.append([queue[qi], st, need, 0, now, []])
+                qi += 1
+            if not active:
+                # idle until the next arrival
+                self.sleep(max(0.0, queue[qi].arrival_s - (self.clock() - t0)))
+                continue
+            max_conc = max(max_conc, len(active))
+            self.ex.step([a[1] for a in active])
+            n_steps += 1
+            builds += len(active)
+            now = self.clock() - t0
+            still = []
+            for a in active:
+                a[3] += 1
+                a[5].append(n_steps - 1)
+                if a[3] >= a[0].n_iter:
+                    res = self.ex.retire(a[1])
+                    reserved -= a[2]
+                    results.append(ServeResult(a[0].rid, a[0].arrival_s, a[4], now, a[3], a[5], res))
+                else:
+                    still.append(a)
+            active = still
+        wall = self.clock() - t0
+        results.sort(key=lambda r: r.rid)
+        return ServeStats(results, wall, n_steps, builds, max_conc, peak)
+
+
+class HipExecutor:
+    """Device executor: one ``hfx`` plan per request, densities of all its SCF
+    iterations and its K resident on the device, one fused build per step.
+
+    Footprint = the plan's static device memory (``hfx_footprint``) + the
+    densities and K + the quartet lists, sized from the screened count of the
+    first density (``hfx_screen_count``) with 25% headroom.  Sizing the head
+    of the queue makes its plan, which waits (outside the accounting) until
+    the request is admitted.  Requests whose static part alone exceeds the
+    limit are rejected by the server."""
+
+    def __init__(self, keep_results: bool = True, flags: Optional[int] = None, list_headroom: float = 1.25):
+        from paper_2009_03555_amd import hfx
+        import torch
+        self.hfx = hfx
+        self.torch = torch
+        self.keep = keep_results
+        self.flags = hfx.HFX_SYNC if flags is None else flags
+        self.headroom = list_headroom
+        self._fp = {}
+        self._pending = {}
+
+    def _densities(self, req: ServeRequest, blocks):
+        import systems
+        out = []
+        for it in range(req.n_iter):
+            vals = systems.perturb_density(req.system, np.asarray(blocks, dtype=np.int64), it)
+            out.append(np.concatenate([v.ravel() for v in vals]) if vals else np.zeros(0))
+        return out
+
+    def static_footprint(self, req: ServeRequest) -> int:
+        dev, _ = self.hfx.hfx_footprint(req.system)
+        return dev
+
+    def footprint(self, req: ServeRequest) -> int:
+        if req.rid in self._fp:
+            return self._fp[req.rid]
+        dev, per_q = self.hfx.hfx_footprint(req.system)
+        # the list part is known only after screening; a plan is made once
+        # here and kept for admit() (its static memory is part of dev)
+        plan = self.hfx.Plan(req.system)
+        D = self._densities(req, plan.blocks)
+        Dd = [self.torch.from_numpy(d).cuda() for d in D]
+        n64, n32 = plan.screen_count(Dd[0])
+        need = dev + 8 * plan.nnz * (req.n_iter + 1) + int(self.headroom * per_q * (n64 + n32))
+        self._fp[req.rid] = need
+        self._pending[req.rid] = (plan, Dd)
+        return need
+
+    def admit(self, req: ServeRequest):
+        self.footprint(req)
+        plan, Dd = self._pending.pop(req.rid)
+        K = self.torch.zeros_like(Dd[0])
+        return {"req": req, "plan": plan, "D": Dd, "K": K, "it": 0}
+
+    def step(self, states) -> None:
+        plans = [s["plan"] for s in states]
+        Ds = [s["D"][s["it"]] for s in states]
+        Ks = [s["K"] for s in states]
+        self.hfx.build_K_multi(plans, Ds, Ks, flags=self.flags)
+        self.torch.cuda.synchronize()
+        for s in states:
+            s["it"] += 1
+
+    def retire(self, state):
+        out = state["K"].cpu().numpy() if self.keep else None
+        state["plan"].destroy()
+        self._fp.pop(state["req"].rid, None)
+        state["D"] = state["K"] = None
+        return out

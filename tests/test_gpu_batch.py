@@ -171,3 +171,32 @@ def test_multi_graph():
         hfx.build_K_multi(plans, Dd, Kd, flags=hfx.HFX_GRAPH)
         for k, r in zip(Kd, sep):
             assert np.max(np.abs(k.cpu().numpy() - r)) <= 1e-13 * max(1.0, np.max(np.abs(r)))
+
+
+# ------------------------------------------------------------ autotuner
+def test_autotune_keeps_results_and_reports_choices():
+    s = _tiny_cell(seed=304).with_(precision="mixed", fp32_cutoff=1e-6)
+    plan = hfx.Plan(s)
+    D = _density(s, plan.blocks)
+    ref, _ = _eager(hfx.Plan(s), D)
+    Dd = torch.from_numpy(D).to(DEV)
+    Kd = torch.full_like(Dd, np.nan)
+    rep = plan.autotune(Dd, Kd, max_quartets=5000)
+    scale = max(1.0, np.max(np.abs(ref)))
+    assert np.max(np.abs(Kd.cpu().numpy() - ref)) <= 1e-9 * scale
+    timed = [r for r in rep if r["candidates"]]
+    assert timed, "no class was timed"
+    for r in timed:
+        assert 0 <= r["chosen"] < len(r["candidates"]) or r["chosen32"] >= 0
+        best = min(ms for (_, f32, _, ms) in r["candidates"] if not f32) if r["chosen"] >= 0 else None
+        if best is not None:
+            assert r["candidates"][r["chosen"]][3] == best
+    # later builds (eager and graph) use the tuned kernels and agree
+    K2 = torch.zeros_like(Dd)
+    plan.build_K(Dd, K2, flags=hfx.HFX_SYNC)
+    plan.build_K(Dd, K2, flags=hfx.HFX_GRAPH)
+    assert np.max(np.abs(K2.cpu().numpy() - ref)) <= 1e-9 * scale
+    o = oracle.Oracle(s.with_(precision="fp64"))
+    o.set_density(D)
+    Kref, _ = o.build_K()
+    assert np.max(np.abs(K2.cpu().numpy() - Kref)) <= 1e-7

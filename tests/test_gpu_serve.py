@@ -1,0 +1,64 @@
+"""GPU: the continuous-batching server.  A request's K is the same alone and
+in a mix of requests that arrive while it runs (within 1e-12 relative: only
+the order of the floating-point atomic additions differs), and equals a
+direct build with its last density."""
+import numpy as np
+import pytest
+
+import systems
+
+torch = pytest.importorskip("torch")
+hfx = pytest.importorskip("paper_2009_03555_amd.hfx")
+from paper_2009_03555_amd.serve import HipExecutor, Server, ServeRequest  # noqa: E402
+
+pytestmark = pytest.mark.gpu
+
+
+def _tiny_cell(seed, **kw):
+    return systems.config2_diamond(seed=seed, n=(1, 1, 1), nprim=2, shells=(0, 1, 2), r_cut=4.6, **kw)
+
+
+def _requests():
+    return [
+        # a build here takes milliseconds: the first request runs 8
+        # iterations, the others arrive within its first one or two
+        ServeRequest(0, _tiny_cell(501), n_iter=8, arrival_s=0.0),
+        ServeRequest(1, systems.config1_molecule(seed=502), n_iter=3, arrival_s=0.0005),
+        ServeRequest(2, _tiny_cell(503).with_(precision="mixed", fp32_cutoff=1e-6), n_iter=3, arrival_s=0.001),
+        ServeRequest(3, systems.random_cluster(5, 504, nprim=2, op="coulomb"), n_iter=2, arrival_s=0.0015),
+        ServeRequest(4, systems.config1_molecule(seed=505).with_(op="erfc", omega=0.2), n_iter=2, arrival_s=0.002),
+    ]
+
+
+def test_alone_equals_in_mix_and_direct_build():
+    reqs = _requests()
+    solo = Server(HipExecutor(), 1 << 40).run([reqs[0]])
+    mix = Server(HipExecutor(), 1 << 40).run(reqs)
+    assert len(mix.results) == len(reqs)
+    assert mix.max_concurrent >= 2, "later arrivals must join the running request"
+    K_solo = solo.results[0].result
+    K_mix = mix.results[0].result
+    scale = max(1.0, np.max(np.abs(K_solo)))
+    assert np.max(np.abs(K_mix - K_solo)) <= 1e-12 * scale
+    # every result equals a direct build with the request's last density
+    for r, res in zip(reqs, mix.results):
+        plan = hfx.Plan(r.system)
+        vals = systems.perturb_density(r.system, plan.blocks.astype(np.int64), r.n_iter - 1)
+        D = torch.from_numpy(np.concatenate([v.ravel() for v in vals])).cuda()
+        K = torch.zeros_like(D)
+        plan.build_K(D, K, flags=hfx.HFX_SYNC)
+        ref = K.cpu().numpy()
+        assert np.max(np.abs(res.result - ref)) <= 1e-12 * max(1.0, np.max(np.abs(ref))), r.rid
+    s = mix.summary()
+    assert s["builds"] == sum(r.n_iter for r in reqs)
+    assert 0 < s["latency_ms_p50"] <= s["latency_ms_p99"]
+
+
+def test_admission_under_a_tight_limit():
+    reqs = _requests()[:3]
+    ex = HipExecutor()
+    need = [ex.footprint(r) for r in reqs]
+    limit = max(need) + min(need) - 1          # never all three at once
+    st = Server(ex, limit).run(reqs)
+    assert st.peak_reserved_bytes <= limit
+    assert len(st.results) == 3

@@ -1,0 +1,119 @@
+"""Scheduler of the continuous-batching server on the host (no device):
+a host executor with known footprints and a virtual clock."""
+import numpy as np
+import pytest
+
+from paper_2009_03555_amd.serve import Server, ServeRequest
+
+
+class VClock:
+    def __init__(self):
+        self.t = 0.0
+
+    def __call__(self):
+        return self.t
+
+    def sleep(self, dt):
+        self.t += max(dt, 0.0)
+
+
+class HostExecutor:
+    """K_it = A @ D_it for a per-request matrix; a step costs a fixed time
+    plus a time per request (a fused launch)."""
+
+    def __init__(self, clock, fp, step_s=1.0, per_req_s=0.1):
+        self.clock, self.fp, self.step_s, self.per_req_s = clock, fp, step_s, per_req_s
+        self.live = {}
+        self.batches = []
+        self.peak_live_bytes = 0
+
+    def static_footprint(self, r):
+        return self.fp[r.rid]
+
+    def footprint(self, r):
+        return self.fp[r.rid]
+
+    def admit(self, r):
+        st = {"r": r, "it": 0, "K": np.zeros(3)}
+        self.live[r.rid] = st
+        self.peak_live_bytes = max(self.peak_live_bytes, sum(self.fp[k] for k in self.live))
+        return st
+
+    def step(self, states):
+        self.batches.append(sorted(s["r"].rid for s in states))
+        for s in states:
+            rng = np.random.Generator(np.random.PCG64(1000 * s["r"].rid + s["it"]))
+            s["K"] = s["K"] + rng.standard_normal(3)
+            s["it"] += 1
+        self.clock.t += self.step_s + self.per_req_s * len(states)
+
+    def retire(self, st):
+        del self.live[st["r"].rid]
+        return st["K"].copy()
+
+
+def _reqs(n, gap, iters=3, seed=0):
+    rng = np.random.Generator(np.random.PCG64(seed))
+    t = np.cumsum(rng.exponential(gap, size=n))
+    return [ServeRequest(rid=i, system=None, n_iter=iters, arrival_s=float(t[i])) for i in range(n)]
+
+
+def _run(reqs, fp, limit, max_batch=64):
+    clk = VClock()
+    ex = HostExecutor(clk, fp)
+    st = Server(ex, limit, max_batch=max_batch, clock=clk, sleep=clk.sleep).run(reqs)
+    return st, ex
+
+
+def test_every_request_gets_its_iterations():
+    reqs = _reqs(20, 0.5, iters=4)
+    st, ex = _run(reqs, {r.rid: 10 for r in reqs}, 1000)
+    assert len(st.results) == 20
+    assert all(r.n_iter == 4 and len(r.steps) == 4 for r in st.results)
+    assert st.builds == 80 == sum(len(b) for b in ex.batches)
+    # consecutive steps: a request is never skipped while admitted
+    assert all(r.steps == list(range(r.steps[0], r.steps[0] + 4)) for r in st.results)
+
+
+def test_memory_limit_is_respected_and_fifo():
+    reqs = _reqs(15, 0.1, iters=3)
+    fp = {r.rid: 30 + 10 * (r.rid % 3) for r in reqs}
+    st, ex = _run(reqs, fp, 100)
+    assert ex.peak_live_bytes <= 100
+    assert st.peak_reserved_bytes <= 100
+    adm = [r.admitted_s for r in sorted(st.results, key=lambda r: r.rid)]
+    assert adm == sorted(adm), "admission is first come, first served"
+
+
+def test_arrivals_join_running_batches():
+    # a long request starts alone; later ones join its steps (continuous batching)
+    reqs = [ServeRequest(0, None, n_iter=10, arrival_s=0.0)] + \
+           [ServeRequest(i, None, n_iter=2, arrival_s=2.0 + i) for i in range(1, 4)]
+    st, ex = _run(reqs, {r.rid: 1 for r in reqs}, 100)
+    assert ex.batches[0] == [0]
+    assert any(len(b) > 1 and 0 in b for b in ex.batches)
+    r0 = st.results[0]
+    assert r0.latency_s < 10 * (1.0 + 0.1 * 4) + 1e-9
+
+
+def test_result_independent_of_mix():
+    # a request's results depend on its own iterations only
+    solo, _ = _run([ServeRequest(7, None, n_iter=5, arrival_s=0.0)], {7: 1}, 10)
+    others = [ServeRequest(100 + r.rid, None, r.n_iter, r.arrival_s) for r in _reqs(10, 0.3, iters=5)]
+    st, _ = _run(others + [ServeRequest(7, None, n_iter=5, arrival_s=1.0)], {r: 1 for r in list(range(100, 110)) + [7]}, 10)
+    got = [r for r in st.results if r.rid == 7][0]
+    assert np.array_equal(got.result, solo.results[0].result)
+
+
+def test_oversized_request_rejected():
+    with pytest.raises(ValueError):
+        _run([ServeRequest(0, None, 1, 0.0)], {0: 11}, 10)
+
+
+def test_latency_percentiles():
+    reqs = _reqs(30, 0.2, iters=2, seed=3)
+    st, _ = _run(reqs, {r.rid: 1 for r in reqs}, 10, max_batch=4)
+    s = st.summary()
+    assert 0 < s["latency_ms_p50"] <= s["latency_ms_p99"]
+    assert s["max_concurrent"] <= 4
+    assert s["builds"] == 60
