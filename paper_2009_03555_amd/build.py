@@ -20,7 +20,7 @@ ARCH = os.environ.get("HFX_OFFLOAD_ARCH", "gfx950")
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 
 # packed FP32 instructions are disabled on purpose (build flags)
-COMMON = [f"--offload-arch={ARCH}", "-O3", "-std=c++17", "-fPIC", "-munsafe-fp-atomics",
+COMMON = [f"--offload-arch={ARCH}", "-O3", "-std=c++20", "-fPIC", "-munsafe-fp-atomics",
           "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
           f"-I{os.path.join(ROOT, 'include')}", f"-I{CSRC}"]
 

@@ -38,6 +38,10 @@ struct LaneShape {
   static constexpr int NS = noff(LS + 1);
   static constexpr int NGRP = 64 / NS;
   static constexpr int NGT = noff(LG + 1) - noff(GL);
+  // read a whole level's coupling operands at once: measured faster where
+  // the registers allow it (grow side up to L = 3, and (dd|dd), which runs
+  // one wave per SIMD either way)
+  static constexpr bool kBatchReads = LG <= 3 || (CB == 5 && CK == 5);
   static constexpr int NE = noff(EB + 1) - noff(LA), NF = noff(FK + 1) - noff(LC);
   static constexpr int NA = ncart(LA), NB = ncart(LB), NC = ncart(LC), ND = ncart(LD);
   // primitive quartets staged per batch: a multiple of the group count
@@ -64,15 +68,14 @@ struct LaneShape {
     for (int d = 1; d <= LD; ++d) r = cmax(r, NA * NB * (noff(FK - d + 1) - noff(LC)) * ncart(d));
     return r;
   }
-  // LDS exchange (XCH = 0) needs the publish buffers; register shuffles
-  // (XCH = 1) only the HRR region
-  template <typename TV, int XCH>
+  // publish buffers during the primitive loop, the HRR region after it
+  template <typename TV>
   __host__ __device__ static constexpr int work_doubles() {
-    return XCH == 0 ? cmax(2 * hrr_r(), (2 * pbl() * 64 * (int)sizeof(TV) + 7) / 8) : 2 * hrr_r();
+    return cmax(2 * hrr_r(), (2 * pbl() * 64 * (int)sizeof(TV) + 7) / 8);
   }
-  template <typename TV, int XCH>
+  template <typename TV>
   __host__ __device__ static constexpr size_t lds_bytes() {
-    return (size_t)(work_doubles<TV, XCH>() + NBATCH * kCoopStage) * sizeof(double);
+    return (size_t)(work_doubles<TV>() + NBATCH * kCoopStage) * sizeof(double);
   }
 };
 
@@ -90,9 +93,9 @@ __device__ __forceinline__ TV sel3v(int d, TV x, TV y, TV z) {
   return d == 0 ? x : (d == 1 ? y : z);
 }
 
-// XCH: how the electron-coupling operand crosses lanes: each level is
-// published to LDS and read back (0; register shuffles, 1, measured slower)
-template <int CB, int CK, int OP, bool KL, typename TV, int XCH>
+// The electron-coupling operands cross lanes through LDS: each level is
+// published and read back (register shuffles measured slower)
+template <int CB, int CK, int OP, bool KL, typename TV>
 __global__ __launch_bounds__(64, HFX_LANE_WAVES) void eri_lane_kernel(const DevSys *__restrict__ sys, int nsys,
                                                       const int64_t *__restrict__ seg, CoopDev cd,
                                                       const uint64_t *__restrict__ list,
@@ -105,7 +108,7 @@ __global__ __launch_bounds__(64, HFX_LANE_WAVES) void eri_lane_kernel(const DevS
   constexpr int XG = KL ? 9 : 15, YG = KL ? 12 : 18, OG2 = KL ? 21 : 23, RG = KL ? 22 : 24;
   extern __shared__ double W[];
   TV *pub = reinterpret_cast<TV *>(W);
-  double *stage = W + SH::template work_doubles<TV, XCH>();
+  double *stage = W + SH::template work_doubles<TV>();
   const int lane = threadIdx.x;
   const bool active = lane < NGRP * NS;
   const int grp = active ? lane / NS : 0;
@@ -146,6 +149,25 @@ __global__ __launch_bounds__(64, HFX_LANE_WAVES) void eri_lane_kernel(const DevS
     cpw[k - 1] = (TV)np;
   }
 
+  // lane-local part of grow component c of level lv, all m:
+  // X_i [g]^(m) + Y_i [g]^(m+1) + N_i(g)/(2 zeta_g) ([g-1_i]^(m) - rho/zeta_g [g-1_i]^(m+1)),
+  // g = t - 1_i the parent in the build direction i of t
+  auto grow_local = [&]<int lv, int c>(TV *V, const TV *gX, const TV *gY, TV o2g, TV rg) {
+    constexpr int MR = LG - lv;
+    constexpr C3 t = cart_of(lv, c);
+    constexpr int i = dir_of(t);
+    constexpr C3 p = sub1(t, i);
+    constexpr int np = pw(p, i);
+    constexpr int pc = cidx(p);
+    constexpr int ppc = np > 0 ? cidx(sub1(p, i)) : 0;
+#pragma unroll
+    for (int m = 0; m <= MR; ++m) {
+      TV v = fma(gY[i], V[SH::vo(lv - 1, pc, m + 1)], gX[i] * V[SH::vo(lv - 1, pc, m)]);
+      if constexpr (np > 0)
+        v = fma((TV)np * o2g, fma(-rg, V[SH::vo(lv - 2, ppc, m + 1)], V[SH::vo(lv - 2, ppc, m)]), v);
+      V[SH::vo(lv, c, m)] = v;
+    }
+  };
   unsigned long long prims = 0;
   const int64_t q0 = seg[0], q1 = seg[nsys];
   for (int64_t qi = q0 + blockIdx.x; qi < q1; qi += gridDim.x) {
@@ -217,7 +239,7 @@ __global__ __launch_bounds__(64, HFX_LANE_WAVES) void eri_lane_kernel(const DevS
 #pragma unroll
         for (int m = 0; m <= LG; ++m) V[SH::vo(0, 0, m)] = cur[m];
         if constexpr (GL == 0) acc[0] += V[0];
-        if constexpr (XCH == 0 && LG > 0) {
+        if constexpr (LG > 0) {
 #pragma unroll
           for (int m = 1; m <= LG; ++m) pub[(m - 1) * 64 + lane] = V[SH::vo(0, 0, m)];
           wave_lds_sync();
@@ -226,32 +248,46 @@ __global__ __launch_bounds__(64, HFX_LANE_WAVES) void eri_lane_kernel(const DevS
           constexpr int lv = decltype(lv_)::value;
           constexpr int MR = LG - lv;
           constexpr int rb = ((lv - 1) & 1) * PBL, wb = (lv & 1) * PBL;
-          sfor<0, ncart(lv)>([&](auto c_) {
-            constexpr int c = decltype(c_)::value;
-            constexpr C3 t = cart_of(lv, c);
-            constexpr int i = dir_of(t);
-            constexpr C3 p = sub1(t, i);
-            constexpr int np = pw(p, i);
-            constexpr int pc = cidx(p);
-            constexpr int ppc = np > 0 ? cidx(sub1(p, i)) : 0;
-            TV R[MR + 1];
+          if constexpr (SH::kBatchReads) {
+            // every electron-coupling operand of the level first (one
+            // wait), the lane-local terms while they arrive, then the
+            // coupling terms
+            TV RL[ncart(lv) * (MR + 1)];
+            sfor<0, ncart(lv)>([&](auto c_) {
+              constexpr int c = decltype(c_)::value;
+              constexpr int i = dir_of(cart_of(lv, c));
+              constexpr int pc = cidx(sub1(cart_of(lv, c), i));
 #pragma unroll
-            for (int m = 0; m <= MR; ++m) {
-              if constexpr (XCH == 0)
-                R[m] = pub[(rb + pc * (MR + 1) + m) * 64 + src[i]];
-              else
-                R[m] = __shfl(V[SH::vo(lv - 1, pc, m + 1)], src[i]);
-            }
+              for (int m = 0; m <= MR; ++m) RL[c * (MR + 1) + m] = pub[(rb + pc * (MR + 1) + m) * 64 + src[i]];
+            });
+            sfor<0, ncart(lv)>([&](auto c_) {
+              constexpr int c = decltype(c_)::value;
+              grow_local.template operator()<lv, c>(V, gX, gY, o2g, rg);
+            });
+            sfor<0, ncart(lv)>([&](auto c_) {
+              constexpr int c = decltype(c_)::value;
+              constexpr int i = dir_of(cart_of(lv, c));
 #pragma unroll
-            for (int m = 0; m <= MR; ++m) {
-              TV v = fma(gY[i], V[SH::vo(lv - 1, pc, m + 1)], gX[i] * V[SH::vo(lv - 1, pc, m)]);
-              if constexpr (np > 0)
-                v = fma((TV)np * o2g, fma(-rg, V[SH::vo(lv - 2, ppc, m + 1)], V[SH::vo(lv - 2, ppc, m)]), v);
-              V[SH::vo(lv, c, m)] = fma(xc[i], R[m], v);
-            }
-            if constexpr (lv >= GL) acc[noff(lv) + c - noff(GL)] += V[SH::vo(lv, c, 0)];
-          });
-          if constexpr (XCH == 0 && lv < LG) {
+              for (int m = 0; m <= MR; ++m)
+                V[SH::vo(lv, c, m)] = fma(xc[i], RL[c * (MR + 1) + m], V[SH::vo(lv, c, m)]);
+              if constexpr (lv >= GL) acc[noff(lv) + c - noff(GL)] += V[SH::vo(lv, c, 0)];
+            });
+          } else {
+            // component by component (register budget of the d-d grow side)
+            sfor<0, ncart(lv)>([&](auto c_) {
+              constexpr int c = decltype(c_)::value;
+              constexpr int i = dir_of(cart_of(lv, c));
+              constexpr int pc = cidx(sub1(cart_of(lv, c), i));
+              TV R[MR + 1];
+#pragma unroll
+              for (int m = 0; m <= MR; ++m) R[m] = pub[(rb + pc * (MR + 1) + m) * 64 + src[i]];
+              grow_local.template operator()<lv, c>(V, gX, gY, o2g, rg);
+#pragma unroll
+              for (int m = 0; m <= MR; ++m) V[SH::vo(lv, c, m)] = fma(xc[i], R[m], V[SH::vo(lv, c, m)]);
+              if constexpr (lv >= GL) acc[noff(lv) + c - noff(GL)] += V[SH::vo(lv, c, 0)];
+            });
+          }
+          if constexpr (lv < LG) {
             sfor<0, ncart(lv)>([&](auto c_) {
               constexpr int c = decltype(c_)::value;
 #pragma unroll
@@ -297,8 +333,8 @@ void launch_lane_t(const CoopDev &cd, const SegLaunch &L) {
   constexpr bool KL = lane_ket<CB, CK>();
   using SH = LaneShape<CB, CK, KL>;
   const int64_t blocks = seg_grid(L, L.nq_hint, 256 * 32);
-  constexpr size_t lds = SH::template lds_bytes<TV, 0>();
-  hipLaunchKernelGGL((eri_lane_kernel<CB, CK, OP, KL, TV, 0>), dim3((unsigned)blocks), dim3(64), lds, L.stream,
+  constexpr size_t lds = SH::template lds_bytes<TV>();
+  hipLaunchKernelGGL((eri_lane_kernel<CB, CK, OP, KL, TV>), dim3((unsigned)blocks), dim3(64), lds, L.stream,
                      L.sys, L.nsys, L.seg, cd, L.list, L.nprim);
 }
 
