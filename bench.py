@@ -115,6 +115,110 @@ def _build_series(plan, Dd, Kd, steps, warmup, label):
     return lat, infos, time.perf_counter() - t0
 
 
+def _dens(system, plan):
+    import systems
+    vals = systems.density_blocks(system, plan.blocks.astype(np.int64))
+    return np.concatenate([v.ravel() for v in vals]) if vals else np.zeros(0)
+
+
+def bench_batch(args):
+    """Many small independent clusters (the batched-launch recipe at a size a
+    bench can run): separate FP64 builds one after the other, against one
+    fused multi-plan build, eager and replayed from a captured graph."""
+    import torch
+    import systems
+    from paper_2009_03555_amd import hfx
+    out = {}
+    for prec in ("fp64", "mixed"):
+        ss = systems.config4_batch(n_clusters=args.n_clusters, n_range=(4, 16), precision=prec)
+        plans = [hfx.Plan(s) for s in ss]
+        Ds = [torch.from_numpy(_dens(s, p)).cuda() for s, p in zip(ss, plans)]
+        Ks = [torch.zeros_like(d) for d in Ds]
+        for p, d, k in zip(plans, Ds, Ks):
+            p.build_K(d, k, flags=hfx.HFX_SYNC)
+        torch.cuda.synchronize()
+        t = time.perf_counter()
+        for _ in range(args.steps):
+            for p, d, k in zip(plans, Ds, Ks):
+                p.build_K(d, k, flags=hfx.HFX_SYNC)
+        sep = (time.perf_counter() - t) / args.steps
+        K_sep = [k.clone() for k in Ks]
+        hfx.build_K_multi(plans, Ds, Ks, flags=hfx.HFX_SYNC)
+        t = time.perf_counter()
+        for _ in range(args.steps):
+            hfx.build_K_multi(plans, Ds, Ks, flags=hfx.HFX_SYNC)
+        fused = (time.perf_counter() - t) / args.steps
+        hfx.build_K_multi(plans, Ds, Ks, flags=hfx.HFX_GRAPH)
+        t = time.perf_counter()
+        for _ in range(args.steps):
+            hfx.build_K_multi(plans, Ds, Ks, flags=hfx.HFX_GRAPH)
+        graph = (time.perf_counter() - t) / args.steps
+        err = max(float(torch.max(torch.abs(a - b)).item()) for a, b in zip(Ks, K_sep))
+        n = len(plans)
+        out[prec] = {"systems": n, "separate_builds_per_s": n / sep, "fused_builds_per_s": n / fused,
+                     "graph_builds_per_s": n / graph, "max_abs_dK_fused_vs_separate": err}
+        print(f"# batch {prec}: separate {sep*1e3:.1f} ms, fused {fused*1e3:.1f} ms, graph {graph*1e3:.1f} ms "
+              f"for {n} systems", file=sys.stderr, flush=True)
+        for p in plans:
+            p.destroy()
+    print(json.dumps({"metric": "HFX builds/s, batched small clusters", "unit": "builds/s",
+                      "value": out["mixed"]["graph_builds_per_s"], "higher_is_better": True, "n_gpus": 1,
+                      "steps": args.steps, "data": "synthetic",
+                      "config": {"workload": f"{args.n_clusters} clusters of 4-16 atoms (s,s,p,p,d / s,s,p, "
+                                             f"4 primitives, Coulomb)"}, "forms": out}))
+
+
+def bench_serve(args):
+    """A seeded Poisson stream of SCF requests (clusters and small cells of the
+    serving recipe at a size a bench can run): one request at a time with
+    plain FP64 builds, against the continuous-batching server (FP64 and
+    mixed precision)."""
+    import torch
+    import systems
+    from paper_2009_03555_amd import hfx
+    from paper_2009_03555_amd.serve import HipExecutor, Server, ServeRequest
+
+    def stream(prec):
+        rq = systems.config5_requests(n_requests=args.n_requests, rate_per_s=args.rate, cluster_range=(6, 24),
+                                      cell_atoms=(8,), n_iter=10, precision=prec, cluster_nprim=3,
+                                      cell_nprim=3)
+        return [ServeRequest(r.rid, r.system, r.n_iter, r.arrival_s) for r in rq]
+
+    out = {}
+    # plain: requests in arrival order, one FP64 build per iteration, synchronised
+    reqs = stream("fp64")
+    ex = HipExecutor(keep_results=False)
+    t0 = time.perf_counter()
+    lat = []
+    builds = 0
+    for r in reqs:
+        now = time.perf_counter() - t0
+        if now < r.arrival_s:
+            time.sleep(r.arrival_s - now)
+        st = ex.admit(r)
+        for it in range(r.n_iter):
+            st["plan"].build_K(st["D"][it], st["K"], flags=hfx.HFX_SYNC)
+            builds += 1
+        ex.retire(st)
+        lat.append(time.perf_counter() - t0 - r.arrival_s)
+    wall = time.perf_counter() - t0
+    out["plain_fp64"] = {"builds_per_s": builds / wall, "latency_ms_p50": float(np.percentile(lat, 50) * 1e3),
+                         "latency_ms_p99": float(np.percentile(lat, 99) * 1e3), "wall_s": wall}
+    print(f"# serve plain fp64: {builds / wall:.1f} builds/s", file=sys.stderr, flush=True)
+    for prec in ("fp64", "mixed"):
+        stt = Server(HipExecutor(keep_results=False), int(args.hbm_gb * (1 << 30))).run(stream(prec))
+        out[f"served_{prec}"] = stt.summary()
+        print(f"# serve {prec}: {stt.builds_per_s:.1f} builds/s", file=sys.stderr, flush=True)
+    torch.cuda.synchronize()
+    print(json.dumps({"metric": "HFX builds/s (p50/p99 latency), served SCF request stream", "unit": "builds/s",
+                      "value": out["served_mixed"]["builds_per_s"], "higher_is_better": True, "n_gpus": 1,
+                      "data": "synthetic",
+                      "config": {"workload": f"{args.n_requests} Poisson requests at {args.rate}/s, clusters of "
+                                             f"6-24 atoms and 8-atom diamond cells, 3 primitives, 10 SCF "
+                                             f"iterations each, HBM limit {args.hbm_gb} GB"},
+                      "forms": out}))
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -126,6 +230,13 @@ def main():
                          "throughput and max|dK| against the FP64 build")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--n-clusters", type=int, default=64, help="batch workload size")
+    ap.add_argument("--n-requests", type=int, default=24, help="serve workload size")
+    ap.add_argument("--rate", type=float, default=50.0, help="serve workload arrivals per second")
+    ap.add_argument("--hbm-gb", type=float, default=200.0, help="serve workload admission limit")
+    ap.add_argument("--copy-gib", type=float, default=0.0,
+                    help="first run one plain device-to-device copy of this many GiB (a reference "
+                         "dispatch of known traffic for hardware-counter runs)")
     args = ap.parse_args()
 
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
@@ -140,6 +251,19 @@ def main():
     if not torch.cuda.is_available():
         raise SystemExit("bench.py needs a HIP device")
     import systems
+    if args.copy_gib > 0:
+        n = int(args.copy_gib * (1 << 30)) // 8
+        src = torch.ones(n, dtype=torch.float64, device="cuda")
+        dst = torch.empty_like(src)
+        torch.cuda.synchronize()
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        print(f"# reference copy: {n * 8} bytes read, {n * 8} bytes written", file=sys.stderr, flush=True)
+        del src, dst
+    if args.workload == "batch":
+        return bench_batch(args)
+    if args.workload == "serve":
+        return bench_serve(args)
 
     prec = "fp64" if args.precision in ("fp64", "both") else "mixed"
     s = workload(args.workload, prec)

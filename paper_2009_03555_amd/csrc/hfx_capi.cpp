@@ -600,8 +600,11 @@ hfx_status upload_plan(hfx_plan_s &P) {
     for (int ck = 0; ck <= cb; ++ck) {
       const int r = region_of(cb, ck);
       // the lane kernel where the one-lane recursion spills or is absent
-      const bool light = (cb == 4 && ck == 1) || (cb == 5 && ck == 1);
-      P.kern[r] = (lane_available(cb, ck) && !light) ? K_LANE : K_REG;
+      // (bra dp or dd with a ket of two or more angular momentum units);
+      // elsewhere the one-lane kernel, measured faster (the autotuner
+      // revisits the choice per plan)
+      const bool heavy = cb >= 4 && class_la(ck) + class_lb(ck) >= 2;
+      P.kern[r] = (heavy || !register_available(cb, ck)) ? K_LANE : K_REG;
       P.kern32[r] = default_kern32(cb, ck, P.kern[r]);
     }
   {

@@ -65,10 +65,19 @@ void launch_eri_f32(int cb, int ck, int op, const SegLaunch &L) {
 #define HFX_DECL_LANE(CB, CK)                                                                          \
   void launch_eri_lane_r##CB##CK(int op, bool f32, const CoopDev &cd, const SegLaunch &L);             \
   int lane_hrr_capacity_r##CB##CK();
+HFX_DECL_LANE(2, 0)
+HFX_DECL_LANE(2, 1)
+HFX_DECL_LANE(2, 2)
+HFX_DECL_LANE(3, 0)
+HFX_DECL_LANE(3, 1)
+HFX_DECL_LANE(3, 2)
+HFX_DECL_LANE(3, 3)
+HFX_DECL_LANE(4, 0)
 HFX_DECL_LANE(4, 1)
 HFX_DECL_LANE(4, 2)
 HFX_DECL_LANE(4, 3)
 HFX_DECL_LANE(4, 4)
+HFX_DECL_LANE(5, 0)
 HFX_DECL_LANE(5, 1)
 HFX_DECL_LANE(5, 2)
 HFX_DECL_LANE(5, 3)
@@ -78,10 +87,19 @@ HFX_DECL_LANE(5, 5)
 
 void launch_eri_lane(int cb, int ck, int op, bool f32, const CoopDev &cd, const SegLaunch &L) {
   switch (cb * 10 + ck) {
+    case 20: launch_eri_lane_r20(op, f32, cd, L); break;
+    case 21: launch_eri_lane_r21(op, f32, cd, L); break;
+    case 22: launch_eri_lane_r22(op, f32, cd, L); break;
+    case 30: launch_eri_lane_r30(op, f32, cd, L); break;
+    case 31: launch_eri_lane_r31(op, f32, cd, L); break;
+    case 32: launch_eri_lane_r32(op, f32, cd, L); break;
+    case 33: launch_eri_lane_r33(op, f32, cd, L); break;
+    case 40: launch_eri_lane_r40(op, f32, cd, L); break;
     case 41: launch_eri_lane_r41(op, f32, cd, L); break;
     case 42: launch_eri_lane_r42(op, f32, cd, L); break;
     case 43: launch_eri_lane_r43(op, f32, cd, L); break;
     case 44: launch_eri_lane_r44(op, f32, cd, L); break;
+    case 50: launch_eri_lane_r50(op, f32, cd, L); break;
     case 51: launch_eri_lane_r51(op, f32, cd, L); break;
     case 52: launch_eri_lane_r52(op, f32, cd, L); break;
     case 53: launch_eri_lane_r53(op, f32, cd, L); break;
@@ -93,10 +111,19 @@ void launch_eri_lane(int cb, int ck, int op, bool f32, const CoopDev &cd, const 
 
 int lane_hrr_capacity(int cb, int ck) {
   switch (cb * 10 + ck) {
+    case 20: return lane_hrr_capacity_r20();
+    case 21: return lane_hrr_capacity_r21();
+    case 22: return lane_hrr_capacity_r22();
+    case 30: return lane_hrr_capacity_r30();
+    case 31: return lane_hrr_capacity_r31();
+    case 32: return lane_hrr_capacity_r32();
+    case 33: return lane_hrr_capacity_r33();
+    case 40: return lane_hrr_capacity_r40();
     case 41: return lane_hrr_capacity_r41();
     case 42: return lane_hrr_capacity_r42();
     case 43: return lane_hrr_capacity_r43();
     case 44: return lane_hrr_capacity_r44();
+    case 50: return lane_hrr_capacity_r50();
     case 51: return lane_hrr_capacity_r51();
     case 52: return lane_hrr_capacity_r52();
     case 53: return lane_hrr_capacity_r53();

@@ -77,9 +77,9 @@ __host__ __device__ constexpr bool register_available(int cb, int ck) {
 void launch_eri(int cb, int ck, int op, const SegLaunch &L);
 void launch_eri_f32(int cb, int ck, int op, const SegLaunch &L);
 
-// lane-per-component kernels (FP64 and FP32) of the classes with a d shell on
-// the bra side and a non-s ket pair
-__host__ __device__ constexpr bool lane_available(int cb, int ck) { return cb >= 4 && ck >= 1; }
+// lane-per-component kernels (FP64 and FP32) of the classes whose bra pair
+// is pp or has a d shell
+__host__ __device__ constexpr bool lane_available(int cb, int ck) { return cb >= 2 && ck <= cb; }
 struct CoopDev;
 void launch_eri_lane(int cb, int ck, int op, bool f32, const CoopDev &cd, const SegLaunch &L);
 // doubles of HRR workspace the lane kernel of the class reserves

@@ -252,7 +252,7 @@ def test_mixed_precision_cluster_config3_recipe():
 # ------------------------------------------------------ kernel variants
 # every ERI kernel variant of the d-shell classes against the oracle
 _VARIANTS = {
-    "lane": "41=lane,42=lane,43=lane,44=lane,51=lane,52=lane,53=lane,54=lane,55=lane",
+    "lane": ",".join(f"{cb}{ck}=lane" for cb in range(2, 6) for ck in range(cb + 1)),
     "coop": "42=coop,43=coop,44=coop,51=coop,52=coop,53=coop,54=coop,55=coop",
     "reg": "41=reg,42=reg,43=reg,51=reg",
 }
