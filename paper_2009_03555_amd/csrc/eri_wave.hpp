@@ -45,12 +45,12 @@ __device__ __forceinline__ void stage_prims(double *stage, int lane, int nbatch,
     const double *b = ppb + (int64_t)ib * kPP;
     const double *k = ppk + (int64_t)ik * kPP;
     const double zeta = b[0], eta = k[0];
-    const double ze = zeta + eta, ize = 1.0 / ze;
+    const double ize = 1.0 / (zeta + eta);
     const double rho = zeta * eta * ize;
     const double PQx = b[1] - (k[1] + gx), PQy = b[2] - (k[2] + gy), PQz = b[3] - (k[3] + gz);
     const double T = rho * (PQx * PQx + PQy * PQy + PQz * PQz);
     // 2 pi^(5/2) / (zeta eta sqrt(zeta + eta)) times the pair factors
-    const double pref = 34.986836655249725693 / (zeta * eta * sqrt(ze)) * b[7] * k[7];
+    const double pref = b[7] * k[7] * sqrt(ize);
     double G[L + 1];
     ladder<L, OP>(T, rho, s.omega2, pref, s.boys, G);
     const double fe = eta * ize, fz = zeta * ize;
@@ -61,7 +61,8 @@ __device__ __forceinline__ void stage_prims(double *stage, int lane, int nbatch,
     st[12] = -fe * PQx; st[13] = -fe * PQy; st[14] = -fe * PQz;
     st[15] = k[4]; st[16] = k[5]; st[17] = k[6];
     st[18] = fz * PQx; st[19] = fz * PQy; st[20] = fz * PQz;
-    st[21] = 0.5 / zeta; st[22] = rho / zeta; st[23] = 0.5 / eta; st[24] = rho / eta; st[25] = 0.5 * ize;
+    // rho/zeta = eta/(zeta+eta), rho/eta = zeta/(zeta+eta)
+    st[21] = b[8]; st[22] = fe; st[23] = k[8]; st[24] = fz; st[25] = 0.5 * ize;
     st[26] = 1.0; st[27] = 0.0;
   }
 }

@@ -421,6 +421,12 @@ hfx_status build_host(hfx_plan_s &P, const hfx_system *s) {
                   std::pow(1.0 + std::sqrt(PA) + rz, la) * std::pow(1.0 + std::sqrt(PB) + rz, lb);
         ppr[q].push_back(e);
       }
+    // device form of the pair factor: sqrt(2 pi^(5/2)) K / zeta, and 1/(2 zeta)
+    for (auto &e : ppr[q]) {
+      e.v[7] = kSqrt2Pi52 * e.v[7] / e.v[0];
+      e.v[8] = 0.5 / e.v[0];
+      e.v[9] = 0.0;
+    }
     std::stable_sort(ppr[q].begin(), ppr[q].end(), [](const PPRec &x, const PPRec &y) { return x.bound > y.bound; });
     int ns = 0;
     for (auto &e : ppr[q]) ns += e.bound >= kPrimDrop;

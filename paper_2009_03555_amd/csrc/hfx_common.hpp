@@ -96,8 +96,12 @@ __host__ __device__ inline uint64_t pack_quartet(uint32_t bra, uint32_t ket, uin
 }
 
 // ------------------------------------------------------ device system view
-// Primitive pair record (8 doubles): zeta, P(3), P-A(3), K = c_a c_b exp(-mu |AB|^2)
-constexpr int kPP = 8;
+// Primitive pair record (10 doubles): zeta, P(3), P-A(3),
+// sqrt(2 pi^(5/2)) K / zeta with K = c_a c_b exp(-mu |AB|^2), 1/(2 zeta), 0.
+// The product of two such K/zeta factors times 1/sqrt(zeta + eta) is the
+// primitive quartet's prefactor, so a quartet needs one division.
+constexpr int kPP = 10;
+constexpr double kSqrt2Pi52 = 5.914967172795612;  // sqrt(2 pi^(5/2))
 
 struct DevSys {
   // shells

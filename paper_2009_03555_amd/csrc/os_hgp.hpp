@@ -286,33 +286,36 @@ __device__ __forceinline__ void prim_sum(const DevSys &s, const double *__restri
                                          const double *__restrict__ ppk, int nk, double gx, double gy,
                                          double gz, int lane, int stride, T *acc) {
   constexpr int L = C::L;
-  const int n = nb * nk;
-  for (int t = lane; t < n; t += stride) {
-    const int ib = t / nk, ik = t - ib * nk;
+  // bra primitive pairs lane, lane + stride, ...; all ket primitive pairs each
+  for (int ib = lane; ib < nb; ib += stride) {
     const double *b = ppb + (int64_t)ib * kPP;
-    const double *k = ppk + (int64_t)ik * kPP;
-    const double zeta = b[0], eta = k[0];
+    const double zeta = b[0];
     const double Px = b[1], Py = b[2], Pz = b[3];
-    const double Qx = k[1] + gx, Qy = k[2] + gy, Qz = k[3] + gz;
-    const double ze = zeta + eta;
-    const double ize = 1.0 / ze;
-    const double rho = zeta * eta * ize;
-    const double PQx = Px - Qx, PQy = Py - Qy, PQz = Pz - Qz;
-    const double T2 = rho * (PQx * PQx + PQy * PQy + PQz * PQz);
-    // 2 pi^(5/2) / (zeta eta sqrt(zeta + eta)) K_ab K_cd
-    const double pref = 34.986836655249725693 / (zeta * eta * sqrt(ze)) * b[7] * k[7];
-    double G[L + 1];
-    ladder<L, OP>(T2, rho, s.omega2, pref, s.boys, G);
-    const double fe = eta * ize, fz = zeta * ize;
-    T Gt[L + 1];
+    const T PA[3] = {(T)b[4], (T)b[5], (T)b[6]};
+    const double kb = b[7];
+    const T o2z = (T)b[8];
+    for (int ik = 0; ik < nk; ++ik) {
+      const double *k = ppk + (int64_t)ik * kPP;
+      const double eta = k[0];
+      const double Qx = k[1] + gx, Qy = k[2] + gy, Qz = k[3] + gz;
+      const double ize = 1.0 / (zeta + eta);
+      const double rho = zeta * eta * ize;
+      const double PQx = Px - Qx, PQy = Py - Qy, PQz = Pz - Qz;
+      const double T2 = rho * (PQx * PQx + PQy * PQy + PQz * PQz);
+      // 2 pi^(5/2) / (zeta eta sqrt(zeta + eta)) K_ab K_cd
+      const double pref = kb * k[7] * sqrt(ize);
+      double G[L + 1];
+      ladder<L, OP>(T2, rho, s.omega2, pref, s.boys, G);
+      const double fe = eta * ize, fz = zeta * ize;
+      T Gt[L + 1];
 #pragma unroll
-    for (int m = 0; m <= L; ++m) Gt[m] = (T)G[m];
-    T PA[3] = {(T)b[4], (T)b[5], (T)b[6]};
-    T WP[3] = {(T)(-fe * PQx), (T)(-fe * PQy), (T)(-fe * PQz)};
-    T QC[3] = {(T)k[4], (T)k[5], (T)k[6]};
-    T WQ[3] = {(T)(fz * PQx), (T)(fz * PQy), (T)(fz * PQz)};
-    vrr_add<C, T>(Gt, PA, WP, QC, WQ, (T)(0.5 / zeta), (T)(rho / zeta), (T)(0.5 / eta), (T)(rho / eta),
-                  (T)(0.5 * ize), acc);
+      for (int m = 0; m <= L; ++m) Gt[m] = (T)G[m];
+      const T WP[3] = {(T)(-fe * PQx), (T)(-fe * PQy), (T)(-fe * PQz)};
+      const T QC[3] = {(T)k[4], (T)k[5], (T)k[6]};
+      const T WQ[3] = {(T)(fz * PQx), (T)(fz * PQy), (T)(fz * PQz)};
+      // rho/zeta = eta/(zeta+eta), rho/eta = zeta/(zeta+eta)
+      vrr_add<C, T>(Gt, PA, WP, QC, WQ, o2z, (T)fe, (T)k[8], (T)fz, (T)(0.5 * ize), acc);
+    }
   }
 }
 
