@@ -228,6 +228,8 @@ def main():
     ap.add_argument("--precision", default="both", choices=["fp64", "mixed", "both"],
                     help="fp64: the plain form only; both: also the mixed-precision form, its "
                          "throughput and max|dK| against the FP64 build")
+    ap.add_argument("--fp32-cutoff", type=float, default=1e-4,
+                    help="mixed form: quartets with Q_IJ*Q_KL below this take the FP32 recursion")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--n-clusters", type=int, default=64, help="batch workload size")
@@ -330,7 +332,7 @@ def main():
     }
     if args.precision == "both":
         K64 = Kd.clone()
-        smx = s.with_(precision="mixed", fp32_cutoff=1e-6, name=s.name)
+        smx = s.with_(precision="mixed", fp32_cutoff=args.fp32_cutoff, name=s.name)
         pmx = hfx.Plan(smx)
         Kmx = torch.zeros_like(Dd)
         pmx.schwarz()

@@ -21,9 +21,6 @@
 #include "eri_wave.hpp"
 #include "launchers.hpp"
 
-#ifndef HFX_LANE_WAVES
-#define HFX_LANE_WAVES 1
-#endif
 
 namespace hfx {
 
@@ -96,7 +93,7 @@ __device__ __forceinline__ TV sel3v(int d, TV x, TV y, TV z) {
 // The electron-coupling operands cross lanes through LDS: each level is
 // published and read back (register shuffles measured slower)
 template <int CB, int CK, int OP, bool KL, typename TV>
-__global__ __launch_bounds__(64, HFX_LANE_WAVES) void eri_lane_kernel(const DevSys *__restrict__ sys, int nsys,
+__global__ __launch_bounds__(64) void eri_lane_kernel(const DevSys *__restrict__ sys, int nsys,
                                                       const int64_t *__restrict__ seg, CoopDev cd,
                                                       const uint64_t *__restrict__ list,
                                                       unsigned long long *__restrict__ nprim) {
