@@ -172,16 +172,17 @@ def bench_serve(args):
     """A seeded Poisson stream of SCF requests (clusters and small cells of the
     serving recipe at a size a bench can run): one request at a time with
     plain FP64 builds, against the continuous-batching server (FP64 and
-    mixed precision)."""
+    mixed precision, with a per-step work budget; and without one, every
+    admitted request in every step)."""
     import torch
     import systems
     from paper_2009_03555_amd import hfx
     from paper_2009_03555_amd.serve import HipExecutor, Server, ServeRequest
 
     def stream(prec):
-        rq = systems.config5_requests(n_requests=args.n_requests, rate_per_s=args.rate, cluster_range=(6, 24),
+        rq = systems.config5_requests(n_requests=args.n_requests, rate_per_s=args.rate, cluster_range=(4, 12),
                                       cell_atoms=(8,), n_iter=10, precision=prec, cluster_nprim=3,
-                                      cell_nprim=3)
+                                      cell_nprim=2)
         return [ServeRequest(r.rid, r.system, r.n_iter, r.arrival_s) for r in rq]
 
     out = {}
@@ -205,17 +206,19 @@ def bench_serve(args):
     out["plain_fp64"] = {"builds_per_s": builds / wall, "latency_ms_p50": float(np.percentile(lat, 50) * 1e3),
                          "latency_ms_p99": float(np.percentile(lat, 99) * 1e3), "wall_s": wall}
     print(f"# serve plain fp64: {builds / wall:.1f} builds/s", file=sys.stderr, flush=True)
-    for prec in ("fp64", "mixed"):
-        stt = Server(HipExecutor(keep_results=False), int(args.hbm_gb * (1 << 30))).run(stream(prec))
-        out[f"served_{prec}"] = stt.summary()
-        print(f"# serve {prec}: {stt.builds_per_s:.1f} builds/s", file=sys.stderr, flush=True)
+    for prec, budget in (("fp64", args.step_quartets), ("mixed", args.step_quartets), ("fp64", 0.0)):
+        stt = Server(HipExecutor(keep_results=False), int(args.hbm_gb * (1 << 30)),
+                     step_budget=budget).run(stream(prec))
+        key = f"served_{prec}" + ("" if budget > 0 else "_every_request_every_step")
+        out[key] = dict(stt.summary(), step_budget_quartets=budget)
+        print(f"# {key}: {stt.builds_per_s:.1f} builds/s", file=sys.stderr, flush=True)
     torch.cuda.synchronize()
     print(json.dumps({"metric": "HFX builds/s (p50/p99 latency), served SCF request stream", "unit": "builds/s",
                       "value": out["served_mixed"]["builds_per_s"], "higher_is_better": True, "n_gpus": 1,
                       "data": "synthetic",
                       "config": {"workload": f"{args.n_requests} Poisson requests at {args.rate}/s, clusters of "
-                                             f"6-24 atoms and 8-atom diamond cells, 3 primitives, 10 SCF "
-                                             f"iterations each, HBM limit {args.hbm_gb} GB"},
+                                             f"4-12 atoms (3 primitives) and 8-atom diamond cells (2 primitives), "
+                                             f"10 SCF iterations each, HBM limit {args.hbm_gb} GB"},
                       "forms": out}))
 
 
@@ -233,9 +236,11 @@ def main():
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--n-clusters", type=int, default=64, help="batch workload size")
-    ap.add_argument("--n-requests", type=int, default=24, help="serve workload size")
-    ap.add_argument("--rate", type=float, default=50.0, help="serve workload arrivals per second")
+    ap.add_argument("--n-requests", type=int, default=40, help="serve workload size")
+    ap.add_argument("--rate", type=float, default=200.0, help="serve workload arrivals per second")
     ap.add_argument("--hbm-gb", type=float, default=200.0, help="serve workload admission limit")
+    ap.add_argument("--step-quartets", type=float, default=2e7,
+                    help="serve workload: screened quartets one scheduler step may take on")
     ap.add_argument("--copy-gib", type=float, default=0.0,
                     help="first run one plain device-to-device copy of this many GiB (a reference "
                          "dispatch of known traffic for hardware-counter runs)")

@@ -20,8 +20,8 @@ The scheduler is independent of the device: an executor object provides
 reject requests that can never fit), ``footprint(request) -> bytes`` (the
 admission size, asked for the head of the queue only), ``admit(request) ->
 state``,
-``step(states)`` (one build for each state, at its current iteration) and
-``retire(state) -> result``.  ``HipExecutor`` is the device executor; tests
+``step(states)`` (one build for each state, at its current iteration),
+``retire(state) -> result`` and, for a step budget, ``cost(state)``.  ``HipExecutor`` is the device executor; tests
 drive the scheduler with a host-only executor and a virtual clock.
 """
 from __future__ import annotations
@@ -83,11 +83,16 @@ class ServeStats:
 class Server:
     """Iteration-level continuous batching under an HBM budget."""
 
-    def __init__(self, executor, hbm_limit_bytes: int, max_batch: int = 64,
+    def __init__(self, executor, hbm_limit_bytes: int, max_batch: int = 64, step_budget: float = 0.0,
                  clock: Optional[Callable[[], float]] = None, sleep: Optional[Callable[[float], None]] = None):
+        """step_budget > 0: a step runs the admitted requests in admission
+        order only while their summed ``executor.cost`` stays within the
+        budget (at least one); the others keep their device state and wait
+        for the next step.  0: every admitted request runs every step."""
         self.ex = executor
         self.limit = int(hbm_limit_bytes)
         self.max_batch = int(max_batch)
+        self.budget = float(step_budget)
         self.clock = clock or time.perf_counter
         self.sleep = sleep or time.sleep
 
@@ -121,13 +126,26 @@ class Server:
                 # idle until the next arrival
                 self.sleep(max(0.0, queue[qi].arrival_s - (self.clock() - t0)))
                 continue
-            max_conc = max(max_conc, len(active))
-            self.ex.step([a[1] for a in active])
+            run = active
+            if self.budget > 0:
+                run, used = [], 0.0
+                for a in active:
+                    c = self.ex.cost(a[1])
+                    if run and used + c > self.budget:
+                        break
+                    run.append(a)
+                    used += c
+            max_conc = max(max_conc, len(run))
+            self.ex.step([a[1] for a in run])
             n_steps += 1
-            builds += len(active)
+            builds += len(run)
             now = self.clock() - t0
+            ran = {id(a) for a in run}
             still = []
             for a in active:
+                if id(a) not in ran:
+                    still.append(a)
+                    continue
                 a[3] += 1
                 a[5].append(n_steps - 1)
                 if a[3] >= a[0].n_iter:
@@ -188,14 +206,18 @@ class HipExecutor:
         n64, n32 = plan.screen_count(Dd[0])
         need = dev + 8 * plan.nnz * (req.n_iter + 1) + int(self.headroom * per_q * (n64 + n32))
         self._fp[req.rid] = need
-        self._pending[req.rid] = (plan, Dd)
+        self._pending[req.rid] = (plan, Dd, n64 + n32)
         return need
 
     def admit(self, req: ServeRequest):
         self.footprint(req)
-        plan, Dd = self._pending.pop(req.rid)
+        plan, Dd, nq = self._pending.pop(req.rid)
         K = self.torch.zeros_like(Dd[0])
-        return {"req": req, "plan": plan, "D": Dd, "K": K, "it": 0}
+        return {"req": req, "plan": plan, "D": Dd, "K": K, "it": 0, "quartets": nq}
+
+    def cost(self, state) -> float:
+        """work of one build of the request: its screened quartet count"""
+        return float(state["quartets"])
 
     def step(self, states) -> None:
         plans = [s["plan"] for s in states]

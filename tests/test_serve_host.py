@@ -21,8 +21,8 @@ class HostExecutor:
     """K_it = A @ D_it for a per-request matrix; a step costs a fixed time
     plus a time per request (a fused launch)."""
 
-    def __init__(self, clock, fp, step_s=1.0, per_req_s=0.1):
-        self.clock, self.fp, self.step_s, self.per_req_s = clock, fp, step_s, per_req_s
+    def __init__(self, clock, fp, step_s=1.0, per_req_s=0.1, work_s=0.0):
+        self.clock, self.fp, self.step_s, self.per_req_s, self.work_s = clock, fp, step_s, per_req_s, work_s
         self.live = {}
         self.batches = []
         self.peak_live_bytes = 0
@@ -45,11 +45,14 @@ class HostExecutor:
             rng = np.random.Generator(np.random.PCG64(1000 * s["r"].rid + s["it"]))
             s["K"] = s["K"] + rng.standard_normal(3)
             s["it"] += 1
-        self.clock.t += self.step_s + self.per_req_s * len(states)
+        self.clock.t += self.step_s + self.per_req_s * len(states) + self.work_s * sum(self.cost(x) for x in states)
 
     def retire(self, st):
         del self.live[st["r"].rid]
         return st["K"].copy()
+
+    def cost(self, st):
+        return 1.0 + st["r"].rid % 3
 
 
 def _reqs(n, gap, iters=3, seed=0):
@@ -58,10 +61,10 @@ def _reqs(n, gap, iters=3, seed=0):
     return [ServeRequest(rid=i, system=None, n_iter=iters, arrival_s=float(t[i])) for i in range(n)]
 
 
-def _run(reqs, fp, limit, max_batch=64):
+def _run(reqs, fp, limit, max_batch=64, budget=0.0, **cost):
     clk = VClock()
-    ex = HostExecutor(clk, fp)
-    st = Server(ex, limit, max_batch=max_batch, clock=clk, sleep=clk.sleep).run(reqs)
+    ex = HostExecutor(clk, fp, **cost)
+    st = Server(ex, limit, max_batch=max_batch, step_budget=budget, clock=clk, sleep=clk.sleep).run(reqs)
     return st, ex
 
 
@@ -117,3 +120,20 @@ def test_latency_percentiles():
     assert 0 < s["latency_ms_p50"] <= s["latency_ms_p99"]
     assert s["max_concurrent"] <= 4
     assert s["builds"] == 60
+
+
+def test_step_budget_bounds_each_step_and_keeps_fifo():
+    # compute-bound steps: a step takes time in proportion to its work
+    work = dict(step_s=0.05, per_req_s=0.0, work_s=1.0)
+    reqs = _reqs(12, 0.05, iters=3, seed=5)
+    st, ex = _run(reqs, {r.rid: 1 for r in reqs}, 100, budget=4.0, **work)
+    assert len(st.results) == 12 and st.builds == 36
+    for b in ex.batches:
+        cost = sum(1.0 + rid % 3 for rid in b)
+        assert len(b) == 1 or cost <= 4.0
+    # requests admitted earlier finish no later than those admitted after them
+    fin = [r.finished_s for r in sorted(st.results, key=lambda r: (r.admitted_s, r.rid))]
+    assert all(a <= b + 1e-12 for a, b in zip(fin, fin[1:]))
+    # and the budgeted schedule has a lower median latency than running everyone every step
+    st_all, _ = _run(reqs, {r.rid: 1 for r in reqs}, 100, **work)
+    assert st.latency_percentile(50) <= st_all.latency_percentile(50)
