@@ -57,6 +57,7 @@ __global__ __launch_bounds__(64) void eri_coop_kernel(const DevSys *__restrict__
   const uint32_t wbase = (uint32_t)(grp * (cd.nw + 1) * 8);
   const int nws = cd.nw + 1;       // workspace doubles incl. the dummy slot
   double *stage = W + P * nws;     // kCoopBatch x kCoopStage
+  int *pfx = reinterpret_cast<int *>(stage + kCoopBatch * kCoopStage);
   // this lane's VRR ops for the whole launch
   uint32_t opA[SH::NR], opB[SH::NR];
   sfor<0, SH::NLV>([&](auto lv_) {
@@ -102,15 +103,21 @@ __global__ __launch_bounds__(64) void eri_coop_kernel(const DevSys *__restrict__
     }
     const double *ppb = s.pp + (int64_t)bpp.x * kPP;
     const double *ppk = s.pp + (int64_t)kpp.x * kPP;
-    const int nk = kpp.y;
-    const int n = bpp.y * nk;
+    QuartetBlocks qb{-1, -1, -1, -1, 0.0};
+    double thr = 0.0;  // the Schwarz mode sums every primitive quartet
+    if constexpr (MODE == 0) {
+      qb = quartet_blocks(s, bi, ki, g1, g2, g3);
+      thr = prim_threshold(qb.pscr);
+    }
+    const int n = prim_prefix(pfx, ppb, bpp.y, ppk, kpp.y, thr, lane);
     prims += (unsigned long long)n;
+    __syncthreads();
     double acc[SH64::SLOTS];
 #pragma unroll
     for (int k = 0; k < SH64::SLOTS; ++k) acc[k] = 0.0;
 
     for (int t0 = 0; t0 < n; t0 += kCoopBatch) {
-      stage_prims<L, OP>(stage, lane, kCoopBatch, t0, n, nk, ppb, ppk, gx, gy, gz, s);
+      stage_prims<L, OP>(stage, lane, kCoopBatch, t0, n, pfx, bpp.y, ppb, ppk, gx, gy, gz, s);
       __syncthreads();
       const int cnt = (n - t0) < kCoopBatch ? (n - t0) : kCoopBatch;
       for (int u0 = 0; u0 < cnt; u0 += P) {
@@ -181,7 +188,7 @@ __global__ __launch_bounds__(64) void eri_coop_kernel(const DevSys *__restrict__
       schwarz_from_w<CB>(W, cd, s, bra, lane);
     } else {
       hrr_w<CB, CK>(W, cd, s, bra, ket, lane);
-      digest_w<CB, CK>(W + cd.out_base, s, bi, ki, bra, ket, g1, g2, g3, lane);
+      digest_w<CB, CK>(W + cd.out_base, s, bi, ki, bra, ket, g1, g2, g3, qb, lane);
     }
     __syncthreads();
   }
@@ -195,7 +202,8 @@ void launch_coop_t(const CoopDev &cd, const SegLaunch &L) {
   if (L.nq_hint == 0) return;
   constexpr int P = coop_parallel(CB, CK);
   const int64_t blocks = seg_grid(L, L.nq_hint, 256 * 32);
-  const size_t lds = ((size_t)P * (cd.nw + 1) + (size_t)kCoopBatch * kCoopStage) * sizeof(double);
+  const size_t lds = ((size_t)P * (cd.nw + 1) + (size_t)kCoopBatch * kCoopStage) * sizeof(double) +
+                     kPfxInts * sizeof(int);
   hipLaunchKernelGGL((eri_coop_kernel<CB, CK, OP, P, 0>), dim3((unsigned)blocks), dim3(64), lds, L.stream, L.sys,
                      L.nsys, L.seg, cd, L.list, L.nprim, 0, (int64_t)0);
 }
@@ -207,7 +215,8 @@ void launch_coop_schwarz_t(const DevSys *sys1, const CoopDev &cd, int p0, int p1
   constexpr int P = coop_parallel(CB, CB);
   const int64_t n = p1 - p0;
   const int64_t blocks = n < 256 * 32 ? n : 256 * 32;
-  const size_t lds = ((size_t)P * (cd.nw + 1) + (size_t)kCoopBatch * kCoopStage) * sizeof(double);
+  const size_t lds = ((size_t)P * (cd.nw + 1) + (size_t)kCoopBatch * kCoopStage) * sizeof(double) +
+                     kPfxInts * sizeof(int);
   hipLaunchKernelGGL((eri_coop_kernel<CB, CB, OP, P, 1>), dim3((unsigned)blocks), dim3(64), lds, st, sys1, 1,
                      (const int64_t *)nullptr, cd, (const uint64_t *)nullptr, (unsigned long long *)nullptr, p0,
                      n);

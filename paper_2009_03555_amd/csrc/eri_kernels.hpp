@@ -124,12 +124,13 @@ __global__ __launch_bounds__(256) void eri_digest_kernel(const DevSys *__restric
       gy = g1 * s.lat[1] + g2 * s.lat[4] + g3 * s.lat[7];
       gz = g1 * s.lat[2] + g2 * s.lat[5] + g3 * s.lat[8];
     }
+    const QuartetBlocks qb = quartet_blocks(s, bi, ki, g1, g2, g3);
     TV acct[C::NACC];
 #pragma unroll
     for (int k = 0; k < C::NACC; ++k) acct[k] = (TV)0;
-    prim_sum<C, OP, TV>(s, s.pp + (int64_t)bpp.x * kPP, bpp.y, s.pp + (int64_t)kpp.x * kPP, kpp.y, gx, gy,
-                        gz, 0, 1, acct);
-    prims += (unsigned long long)bpp.y * kpp.y;
+    prims += (unsigned long long)prim_sum<C, OP, TV>(s, s.pp + (int64_t)bpp.x * kPP, bpp.y,
+                                                     s.pp + (int64_t)kpp.x * kPP, kpp.y, gx, gy, gz, 0, 1, acct,
+                                                     prim_threshold(qb.pscr));
     double acc[C::NACC];
 #pragma unroll
     for (int k = 0; k < C::NACC; ++k) acc[k] = (double)acct[k];
@@ -139,19 +140,11 @@ __global__ __launch_bounds__(256) void eri_digest_kernel(const DevSys *__restric
     double CD[3] = {kg[0], kg[1], kg[2]};
     double out[C::NOUT];
     hrr<C>(acc, AB, CD, out);
-    int nB1, nB2, nB3, nD1, nD2, nD3;
-    unpack_img8(bi.z, nB1, nB2, nB3);
-    unpack_img8(ki.z, nD1, nD2, nD3);
-    const int A = bi.x, B = bi.y, Cs = ki.x, Ds = ki.y;
-    const int bAC = lookup(s, A, Cs, g1, g2, g3);
-    const int bAD = lookup(s, A, Ds, g1 + nD1, g2 + nD2, g3 + nD3);
-    const int bBC = lookup(s, B, Cs, g1 - nB1, g2 - nB2, g3 - nB3);
-    const int bBD = lookup(s, B, Ds, g1 + nD1 - nB1, g2 + nD2 - nB2, g3 + nD3 - nB3);
     double w = 1.0;
     if (bi.w & 1) w *= 0.5;
     if (ki.w & 1) w *= 0.5;
     if (bra == ket && g1 == 0 && g2 == 0 && g3 == 0) w *= 0.5;
-    digest<C>(s, bAC, bAD, bBC, bBD, out, w, Dc, K4);
+    digest<C>(s, qb.AC, qb.AD, qb.BC, qb.BD, out, w, Dc, K4);
   }
   // one counter update per thread
   prims += __shfl_xor(prims, 1);

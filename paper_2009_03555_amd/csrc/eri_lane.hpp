@@ -72,7 +72,7 @@ struct LaneShape {
   }
   template <typename TV>
   __host__ __device__ static constexpr size_t lds_bytes() {
-    return (size_t)(work_doubles<TV>() + NBATCH * kCoopStage) * sizeof(double);
+    return (size_t)(work_doubles<TV>() + NBATCH * kCoopStage) * sizeof(double) + kPfxInts * sizeof(int);
   }
 };
 
@@ -92,8 +92,16 @@ __device__ __forceinline__ TV sel3v(int d, TV x, TV y, TV z) {
 
 // The electron-coupling operands cross lanes through LDS: each level is
 // published and read back (register shuffles measured slower)
+// two waves per SIMD wanted: the register budget is then 256 per lane; the
+// (dd|dd) kernel needs more and runs one wave per SIMD
+template <int CB, int CK>
+constexpr int lane_waves() {
+  return (CB == 5 && CK == 5) ? 1 : 2;
+}
+
 template <int CB, int CK, int OP, bool KL, typename TV>
-__global__ __launch_bounds__(64) void eri_lane_kernel(const DevSys *__restrict__ sys, int nsys,
+__global__ __attribute__((amdgpu_flat_work_group_size(64, 64), amdgpu_waves_per_eu(lane_waves<CB, CK>())))
+void eri_lane_kernel(const DevSys *__restrict__ sys, int nsys,
                                                       const int64_t *__restrict__ seg, CoopDev cd,
                                                       const uint64_t *__restrict__ list,
                                                       unsigned long long *__restrict__ nprim) {
@@ -106,6 +114,7 @@ __global__ __launch_bounds__(64) void eri_lane_kernel(const DevSys *__restrict__
   extern __shared__ double W[];
   TV *pub = reinterpret_cast<TV *>(W);
   double *stage = W + SH::template work_doubles<TV>();
+  int *pfx = reinterpret_cast<int *>(stage + NBATCH * kCoopStage);
   const int lane = threadIdx.x;
   const bool active = lane < NGRP * NS;
   const int grp = active ? lane / NS : 0;
@@ -183,15 +192,18 @@ __global__ __launch_bounds__(64) void eri_lane_kernel(const DevSys *__restrict__
     }
     const double *ppb = s.pp + (int64_t)bpp.x * kPP;
     const double *ppk = s.pp + (int64_t)kpp.x * kPP;
-    const int nk = kpp.y;
-    const int n = bpp.y * nk;
+    // with a d-d grow side the digest looks its blocks up again, so that
+    // nothing of this stays live through the primitive loop (registers)
+    const QuartetBlocks qb = quartet_blocks(s, bi, ki, g1, g2, g3);
+    const int n = prim_prefix(pfx, ppb, bpp.y, ppk, kpp.y, prim_threshold(qb.pscr), lane);
     prims += (unsigned long long)n;
+    __syncthreads();
     TV acc[NGT];
 #pragma unroll
     for (int k = 0; k < NGT; ++k) acc[k] = (TV)0;
 
     for (int t0 = 0; t0 < n; t0 += NBATCH) {
-      stage_prims<L, OP>(stage, lane, NBATCH, t0, n, nk, ppb, ppk, gx, gy, gz, s);
+      stage_prims<L, OP>(stage, lane, NBATCH, t0, n, pfx, bpp.y, ppb, ppk, gx, gy, gz, s);
       __syncthreads();
       const int cnt = (n - t0) < NBATCH ? (n - t0) : NBATCH;
       for (int u0 = 0; u0 < cnt; u0 += NGRP) {
@@ -312,7 +324,10 @@ __global__ __launch_bounds__(64) void eri_lane_kernel(const DevSys *__restrict__
     });
     __syncthreads();
     hrr_w<CB, CK>(W, cd, s, bra, ket, lane);
-    digest_w<CB, CK>(W + cd.out_base, s, bi, ki, bra, ket, g1, g2, g3, lane);
+    if constexpr (LG <= 3)
+      digest_w<CB, CK>(W + cd.out_base, s, bi, ki, bra, ket, g1, g2, g3, qb, lane);
+    else
+      digest_w<CB, CK>(W + cd.out_base, s, bi, ki, bra, ket, g1, g2, g3, quartet_blocks(s, bi, ki, g1, g2, g3), lane);
     __syncthreads();
   }
   if (lane == 0 && prims) atomicAdd(nprim, prims);

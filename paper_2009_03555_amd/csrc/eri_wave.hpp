@@ -33,15 +33,57 @@ __device__ __forceinline__ double lds(const char *base, uint32_t byte_off) {
 //   26 1.0  27 0.0 (coefficients of an identity step)
 constexpr int kCoopBatch = 16;  // batch of the cooperative kernel
 constexpr int kCoopStage = 28;
+// LDS ints for the prefix sums of a ragged primitive-quartet set (<= 64 + 1)
+constexpr int kPfxInts = kMaxPrim * kMaxPrim + 2;
+
+// The primitive quartets of a contracted quartet that pass the bound
+// threshold thr (0: all): bra primitive pair ib pairs with the first cnt(ib)
+// ket primitive pairs (records sorted by bound).  Lane ib counts its ket
+// pairs by bisection; pfx (nb + 1 ints, LDS) gets the exclusive prefix sums.
+// Returns the number of primitive quartets (same in every lane).
+__device__ __forceinline__ int prim_prefix(int *pfx, const double *__restrict__ ppb, int nb,
+                                           const double *__restrict__ ppk, int nk, double thr, int lane) {
+  int c = 0;
+  if (lane < nb) {
+    const double bthr = thr / ppb[(int64_t)lane * kPP + 9];
+    int lo = 0, hi = nk;  // first ket pair below bthr
+    while (lo < hi) {
+      const int mid = (lo + hi) >> 1;
+      if (ppk[(int64_t)mid * kPP + 9] < bthr)
+        hi = mid;
+      else
+        lo = mid + 1;
+    }
+    c = lo;
+  }
+  int x = c;
+#pragma unroll
+  for (int o = 1; o < 64; o <<= 1) {
+    const int y = __shfl_up(x, o, 64);
+    if (lane >= o) x += y;
+  }
+  if (lane < nb) pfx[lane + 1] = x;
+  if (lane == 0) pfx[0] = 0;
+  return __shfl(x, 63, 64);
+}
 
 // lanes 0 .. nbatch-1 stage primitive quartets t0 .. t0+nbatch-1 (those < n)
+// of the set described by pfx
 template <int L, int OP>
-__device__ __forceinline__ void stage_prims(double *stage, int lane, int nbatch, int t0, int n, int nk,
-                                            const double *__restrict__ ppb, const double *__restrict__ ppk,
+__device__ __forceinline__ void stage_prims(double *stage, int lane, int nbatch, int t0, int n, const int *pfx,
+                                            int nb, const double *__restrict__ ppb, const double *__restrict__ ppk,
                                             double gx, double gy, double gz, const DevSys &s) {
   const int t = t0 + lane;
   if (lane < nbatch && t < n) {
-    const int ib = t / nk, ik = t - ib * nk;
+    int lo = 0, hi = nb;  // last ib with pfx[ib] <= t
+    while (hi - lo > 1) {
+      const int mid = (lo + hi) >> 1;
+      if (pfx[mid] <= t)
+        lo = mid;
+      else
+        hi = mid;
+    }
+    const int ib = lo, ik = t - pfx[lo];
     const double *b = ppb + (int64_t)ib * kPP;
     const double *k = ppk + (int64_t)ik * kPP;
     const double zeta = b[0], eta = k[0];
@@ -107,19 +149,12 @@ __device__ __forceinline__ void schwarz_from_w(double *W, const CoopDev &cd, con
 // (row-major a, b, c, d) into K4, lanes over the output elements of each.
 template <int CB, int CK>
 __device__ __forceinline__ void digest_w(const double *v, const DevSys &s, int4 bi, int4 ki, int bra, int ket, int g1,
-                                         int g2, int g3, int lane) {
+                                         int g2, int g3, const QuartetBlocks &qb, int lane) {
   constexpr int NA = ncart(class_la(CB)), NB = ncart(class_lb(CB)), NC = ncart(class_la(CK)),
                 ND = ncart(class_lb(CK));
   const double *__restrict__ Dc = s.Dc;
   double *__restrict__ K4 = s.K4;
-  int nB1, nB2, nB3, nD1, nD2, nD3;
-  unpack_img8(bi.z, nB1, nB2, nB3);
-  unpack_img8(ki.z, nD1, nD2, nD3);
-  const int A = bi.x, B = bi.y, Cs = ki.x, Ds = ki.y;
-  const int bAC = lookup(s, A, Cs, g1, g2, g3);
-  const int bAD = lookup(s, A, Ds, g1 + nD1, g2 + nD2, g3 + nD3);
-  const int bBC = lookup(s, B, Cs, g1 - nB1, g2 - nB2, g3 - nB3);
-  const int bBD = lookup(s, B, Ds, g1 + nD1 - nB1, g2 + nD2 - nB2, g3 + nD3 - nB3);
+  const int bAC = qb.AC, bAD = qb.AD, bBC = qb.BC, bBD = qb.BD;
   double w = 1.0;
   if (bi.w & 1) w *= 0.5;
   if (ki.w & 1) w *= 0.5;

@@ -425,7 +425,7 @@ hfx_status build_host(hfx_plan_s &P, const hfx_system *s) {
     for (auto &e : ppr[q]) {
       e.v[7] = kSqrt2Pi52 * e.v[7] / e.v[0];
       e.v[8] = 0.5 / e.v[0];
-      e.v[9] = 0.0;
+      e.v[9] = e.bound;
     }
     std::stable_sort(ppr[q].begin(), ppr[q].end(), [](const PPRec &x, const PPRec &y) { return x.bound > y.bound; });
     int ns = 0;

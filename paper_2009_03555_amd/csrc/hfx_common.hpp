@@ -97,10 +97,16 @@ __host__ __device__ inline uint64_t pack_quartet(uint32_t bra, uint32_t ket, uin
 
 // ------------------------------------------------------ device system view
 // Primitive pair record (10 doubles): zeta, P(3), P-A(3),
-// sqrt(2 pi^(5/2)) K / zeta with K = c_a c_b exp(-mu |AB|^2), 1/(2 zeta), 0.
+// sqrt(2 pi^(5/2)) K / zeta with K = c_a c_b exp(-mu |AB|^2), 1/(2 zeta), and
+// B, an upper bound of sqrt(|[p|p]|) over the pair's Cartesian components.
 // The product of two such K/zeta factors times 1/sqrt(zeta + eta) is the
-// primitive quartet's prefactor, so a quartet needs one division.
+// primitive quartet's prefactor, so a quartet needs one division.  A pair's
+// records are sorted by B, largest first.
 constexpr int kPP = 10;
+// A primitive quartet is skipped when B_bra B_ket P_scr < kPrimQuartetDrop:
+// every integral it adds is below B_bra B_ket (Cauchy-Schwarz), so each of the
+// at most 36 terms it adds to a K element is below 36 times this.
+constexpr double kPrimQuartetDrop = 1e-20;
 constexpr double kSqrt2Pi52 = 5.914967172795612;  // sqrt(2 pi^(5/2))
 
 struct DevSys {
@@ -153,6 +159,37 @@ __device__ __forceinline__ int plan_of(const int64_t *__restrict__ seg, int nsys
       hi = mid;
   }
   return lo;
+}
+
+__device__ __forceinline__ int img_index(const DevSys &s, int a, int b, int c);
+__device__ __forceinline__ int lookup(const DevSys &s, int I, int J, int a, int b, int c);
+
+// The four digest blocks of quartet (A^0 B^nB | C^G D^(G+nD)): AC, AD, BC,
+// BD (-1 if outside the pattern), and P_scr = the largest of their P_max.
+struct QuartetBlocks {
+  int AC, AD, BC, BD;
+  double pscr;
+};
+__device__ __forceinline__ QuartetBlocks quartet_blocks(const DevSys &s, int4 bi, int4 ki, int g1, int g2, int g3) {
+  int nB1, nB2, nB3, nD1, nD2, nD3;
+  unpack_img8(bi.z, nB1, nB2, nB3);
+  unpack_img8(ki.z, nD1, nD2, nD3);
+  QuartetBlocks qb;
+  qb.AC = lookup(s, bi.x, ki.x, g1, g2, g3);
+  qb.AD = lookup(s, bi.x, ki.y, g1 + nD1, g2 + nD2, g3 + nD3);
+  qb.BC = lookup(s, bi.y, ki.x, g1 - nB1, g2 - nB2, g3 - nB3);
+  qb.BD = lookup(s, bi.y, ki.y, g1 + nD1 - nB1, g2 + nD2 - nB2, g3 + nD3 - nB3);
+  double p = 0.0;
+  if (qb.AC >= 0) p = fmax(p, s.pmax[qb.AC]);
+  if (qb.AD >= 0) p = fmax(p, s.pmax[qb.AD]);
+  if (qb.BC >= 0) p = fmax(p, s.pmax[qb.BC]);
+  if (qb.BD >= 0) p = fmax(p, s.pmax[qb.BD]);
+  qb.pscr = p;
+  return qb;
+}
+// bound below which a primitive quartet of this quartet is skipped
+__device__ __forceinline__ double prim_threshold(double pscr) {
+  return pscr > 0.0 ? kPrimQuartetDrop / pscr : 1e300;
 }
 
 __device__ __forceinline__ int img_index(const DevSys &s, int a, int b, int c) {

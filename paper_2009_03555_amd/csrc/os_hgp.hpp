@@ -282,20 +282,27 @@ __device__ __forceinline__ void hrr(const double *acc, const double *AB, const d
 // for the mixed-precision path (the ladder, including the Boys function, and
 // the prefactor are always evaluated in double and rounded once).
 template <class C, int OP, typename T = double>
-__device__ __forceinline__ void prim_sum(const DevSys &s, const double *__restrict__ ppb, int nb,
-                                         const double *__restrict__ ppk, int nk, double gx, double gy,
-                                         double gz, int lane, int stride, T *acc) {
+__device__ __forceinline__ int prim_sum(const DevSys &s, const double *__restrict__ ppb, int nb,
+                                        const double *__restrict__ ppk, int nk, double gx, double gy,
+                                        double gz, int lane, int stride, T *acc, double thr = 0.0) {
   constexpr int L = C::L;
-  // bra primitive pairs lane, lane + stride, ...; all ket primitive pairs each
+  int done = 0;
+  if (nk <= 0) return 0;
+  // bra primitive pairs lane, lane + stride, ...; the ket primitive pairs of
+  // each down to the bound threshold (records sorted by bound)
   for (int ib = lane; ib < nb; ib += stride) {
     const double *b = ppb + (int64_t)ib * kPP;
+    if (b[9] * ppk[9] < thr) break;
     const double zeta = b[0];
     const double Px = b[1], Py = b[2], Pz = b[3];
     const T PA[3] = {(T)b[4], (T)b[5], (T)b[6]};
     const double kb = b[7];
     const T o2z = (T)b[8];
+    const double bthr = thr / b[9];
     for (int ik = 0; ik < nk; ++ik) {
       const double *k = ppk + (int64_t)ik * kPP;
+      if (k[9] < bthr) break;
+      ++done;
       const double eta = k[0];
       const double Qx = k[1] + gx, Qy = k[2] + gy, Qz = k[3] + gz;
       const double ize = 1.0 / (zeta + eta);
@@ -317,6 +324,7 @@ __device__ __forceinline__ void prim_sum(const DevSys &s, const double *__restri
       vrr_add<C, T>(Gt, PA, WP, QC, WQ, o2z, (T)fe, (T)k[8], (T)fz, (T)(0.5 * ize), acc);
     }
   }
+  return done;
 }
 
 }  // namespace hfx
