@@ -160,6 +160,19 @@ hfx_status hfx_build_K(hfx_plan_t plan, const double *d_dev, double *k_dev, uint
 hfx_status hfx_build_K_multi(int32_t n, const hfx_plan_t *plans, const double *const *d_dev,
                              double *const *k_dev, uint32_t flags, hfx_build_info *info);
 
+/* K from a caller-chosen subset of the unique quartets only (a shard of the
+ * screened list, or a sample for verification): the same density transform,
+ * ERI and digest kernels (the plan's kernel choices) and finalisation as
+ * hfx_build_K, over the n quartets in quartets_host (host memory, the
+ * encoding of hfx_export what = 1: bra pair | ket pair << 24 | translation
+ * << 48, any order; duplicates are evaluated twice).  The quartet screening
+ * predicate is not applied (the caller chose the quartets); the primitive-
+ * quartet bound is, with P_scr from d_dev.  Synchronous.  HFX_ERR_INVALID if
+ * a pair index is out of range or a quartet's bra pair class is below its
+ * ket pair class. */
+hfx_status hfx_build_K_subset(hfx_plan_t plan, const double *d_dev, double *k_dev, const uint64_t *quartets_host,
+                              int64_t n);
+
 /* Screened quartet count of a build with density d_dev, without building:
  * density transform, P_max and the counting pass of the screening only.
  * n64: quartets of the FP64 list, n32: of the FP32 list (mixed precision,

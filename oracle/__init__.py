@@ -71,6 +71,8 @@ def lib():
         L.oracle_quartets.argtypes = [ctypes.c_void_p, ctypes.c_int, ctypes.c_int64, i32p, dp]
         L.oracle_eval_quartets.restype = ctypes.c_int64
         L.oracle_eval_quartets.argtypes = [ctypes.c_void_p, ctypes.c_int64, i32p, dp]
+        L.oracle_K_from_quartets.restype = ctypes.c_int64
+        L.oracle_K_from_quartets.argtypes = [ctypes.c_void_p, ctypes.c_int64, i32p, dp]
         _lib = L
     return _lib
 
@@ -218,6 +220,15 @@ class Oracle:
         cs = ctypes.c_double(0.0)
         n = lib().oracle_eval_quartets(self.h, len(rows), _p(rows, ctypes.c_int32), ctypes.byref(cs))
         return int(n), float(cs.value)
+
+    def K_from_quartets(self, rows: np.ndarray):
+        """K (pattern layout) from the given ordered quartets only, each
+        adding its plain term of Eq. H-HFX (no screening); returns (K, number
+        of rows whose K and D blocks exist).  Needs set_density first."""
+        rows = np.ascontiguousarray(rows, dtype=np.int32).reshape(-1, 13)
+        K = np.zeros(self.nnz)
+        n = lib().oracle_K_from_quartets(self.h, len(rows), _p(rows, ctypes.c_int32), _p(K))
+        return K, int(n)
 
     def sample_quartets(self, n: int, seed: int = 0) -> np.ndarray:
         """n ordered quartets (I^0 J^N | K^G L^H) drawn uniformly from the

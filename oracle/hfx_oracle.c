@@ -642,6 +642,66 @@ int64_t oracle_build_K(void *h, int64_t nreq, const int64_t *req, int screened, 
   return evaluated;
 }
 
+/* K from the given ordered quartets only (rows of 13 ints as in
+ * oracle_quartets), without screening: each row (I^0 J^N | K^G L^H) adds
+ * (mu nu | lambda sigma) D^{H-N}_{nu sigma} to K^G_{mu lambda}, the plain
+ * term of Eq. H-HFX; rows whose K or D block lies outside the pattern add
+ * nothing.  k_out (pattern layout, nnz values) is overwritten.  Returns the
+ * number of rows that contributed. */
+int64_t oracle_K_from_quartets(void *h, int64_t n, const int32_t *rows, double *k_out) {
+  osys *s = (osys *)h;
+  double *kc = (double *)calloc((size_t)s->nnz_c, sizeof(double));
+  int64_t used = 0;
+  double eri[1296];
+  for (int64_t r = 0; r < n; ++r) {
+    const int32_t *o = rows + 13 * r;
+    int I = o[0], J = o[1], N[3] = {o[2], o[3], o[4]};
+    int K = o[5], L = o[6], M[3] = {o[7], o[8], o[9]};
+    int G[3] = {o[10], o[11], o[12]};
+    int H[3] = {G[0] + M[0], G[1] + M[1], G[2] + M[2]};
+    int64_t kb = find_block(s, I, K, G[0], G[1], G[2]);
+    int64_t db = find_block(s, J, L, H[0] - N[0], H[1] - N[1], H[2] - N[2]);
+    if (kb < 0 || db < 0) continue;
+    int z[3] = {0, 0, 0};
+    oshell A, B, C, D;
+    make_shell(s, I, z, &A);
+    make_shell(s, J, N, &B);
+    make_shell(s, K, G, &C);
+    make_shell(s, L, H, &D);
+    oracle_eri_quartet(&A, &B, &C, &D, s->op, s->omega, eri);
+    int na = ncart(A.l), nb = ncart(B.l), nc = ncart(C.l), nd = ncart(D.l);
+    const double *dc = s->Dc + s->blk_coff[db];
+    double *ko = kc + s->blk_coff[kb];
+    for (int a = 0; a < na; ++a)
+      for (int c = 0; c < nc; ++c) {
+        double acc = 0.0;
+        for (int b = 0; b < nb; ++b)
+          for (int d = 0; d < nd; ++d) acc += eri[((a * nb + b) * nc + c) * nd + d] * dc[b * nd + d];
+        ko[a * nc + c] += acc;
+      }
+    ++used;
+  }
+  for (int64_t kb = 0; kb < s->nblk; ++kb) {
+    const int32_t *x = s->blk + 5 * kb;
+    int I = x[0], K = x[1];
+    int ci = ncart(s->sh_l[I]), ck = ncart(s->sh_l[K]);
+    double TI[36], TK[36];
+    int ri = sph_T(s->sh_l[I], s->spherical, TI);
+    int rk = sph_T(s->sh_l[K], s->spherical, TK);
+    const double *kcb = kc + s->blk_coff[kb];
+    double *ko = k_out + s->blk_off[kb];
+    for (int m = 0; m < ri; ++m)
+      for (int q = 0; q < rk; ++q) {
+        double v = 0.0;
+        for (int a = 0; a < ci; ++a)
+          for (int c = 0; c < ck; ++c) v += TI[m * ci + a] * kcb[a * ck + c] * TK[q * ck + c];
+        ko[m * rk + q] = v;
+      }
+  }
+  free(kc);
+  return used;
+}
+
 /* Ordered quartets (I^0 J^N | K^G L^H) kept by the predicate, for bra and
  * ket pairs in the pattern and ket translations G in the box |G_i| <= gR
  * (G = 0 for molecules).  Row r of out_i holds 13 ints

@@ -1266,6 +1266,63 @@ hfx_status hfx_build_K(hfx_plan_t plan, const double *d_dev, double *k_dev, uint
   return run_batch(*P.self_batch, &d_dev, &k_dev, flags, info);
 }
 
+hfx_status hfx_build_K_subset(hfx_plan_t plan, const double *d_dev, double *k_dev, const uint64_t *quartets_host,
+                              int64_t n) {
+  if (!valid_plan(plan)) return fail(HFX_ERR_STATE, "invalid or destroyed plan");
+  if (!d_dev || !k_dev || n < 0 || (n > 0 && !quartets_host)) return fail(HFX_ERR_INVALID, "bad arguments");
+  hfx_plan_s &P = *plan;
+  if (!P.schwarz_done) {
+    hfx_status st = run_schwarz(P);
+    if (st != HFX_OK) return st;
+  }
+  // class segments on the host
+  const int64_t npairs = (int64_t)P.pr_info.size();
+  std::vector<std::vector<uint64_t>> by(kNQuartetClass);
+  for (int64_t i = 0; i < n; ++i) {
+    const uint64_t q = quartets_host[i];
+    const int64_t bra = (int64_t)(q & 0xFFFFFFull), ket = (int64_t)((q >> 24) & 0xFFFFFFull);
+    if (bra >= npairs || ket >= npairs) return fail(HFX_ERR_INVALID, "quartet pair index out of range");
+    const int cb = pair_class(P.sh_l[P.pr_info[bra].x], P.sh_l[P.pr_info[bra].y]);
+    const int ck = pair_class(P.sh_l[P.pr_info[ket].x], P.sh_l[P.pr_info[ket].y]);
+    if (cb < ck) return fail(HFX_ERR_INVALID, "quartet with bra pair class below its ket pair class");
+    by[region_of(cb, ck)].push_back(q);
+  }
+  std::vector<uint64_t> list;
+  std::vector<int64_t> seg(2 * kNQuartetClass);
+  for (int r = 0; r < kNQuartetClass; ++r) {
+    seg[2 * r] = (int64_t)list.size();
+    list.insert(list.end(), by[r].begin(), by[r].end());
+    seg[2 * r + 1] = (int64_t)list.size();
+  }
+  DevMem mem;
+  uint64_t *d_list = nullptr;
+  int64_t *d_seg = nullptr;
+  unsigned long long *d_np = nullptr;
+  HIPCHK(mem.alloc(&d_list, list.size() + 1));
+  HIPCHK(mem.alloc(&d_seg, seg.size()));
+  HIPCHK(mem.alloc(&d_np, kNQuartetClass));
+  const hipStream_t st = P.stream;
+  if (!list.empty()) HIPCHK(hipMemcpyAsync(d_list, list.data(), list.size() * 8, hipMemcpyHostToDevice, st));
+  HIPCHK(hipMemcpyAsync(d_seg, seg.data(), seg.size() * 8, hipMemcpyHostToDevice, st));
+  launch_zero_u64(d_np, kNQuartetClass, st);
+  launch_zero_u64(P.d_pglob, 1, st);
+  launch_density(P.ds, (int64_t)P.blocks.size(), P.d_blk_IJ, P.d_blk_off, P.d_partner, P.d_canon, P.sph, d_dev, P.d_Dc,
+                 st);
+  launch_zero(P.d_K4, P.nnz_c, st);
+  for (int cb = 0; cb < kNPairClass; ++cb)
+    for (int ck = 0; ck <= cb; ++ck) {
+      const int r = region_of(cb, ck);
+      const int64_t cnt = seg[2 * r + 1] - seg[2 * r];
+      if (cnt == 0) continue;
+      SegLaunch L{P.d_sys1, 1, d_seg + 2 * r, d_list, d_np + r, cnt, st, P.grid[r]};
+      launch_variant(P.kern[r], cb, ck, P.op, P.coop[r], L);
+    }
+  launch_finalize(P.ds, (int64_t)P.blocks.size(), P.d_blk_IJ, P.d_blk_off, P.d_partner, P.sph, P.d_K4, k_dev, st);
+  HIPCHK(hipGetLastError());
+  HIPCHK(hipStreamSynchronize(st));
+  return HFX_OK;
+}
+
 hfx_status hfx_screen_count(hfx_plan_t plan, const double *d_dev, int64_t *n64, int64_t *n32) {
   if (!valid_plan(plan)) return fail(HFX_ERR_STATE, "invalid or destroyed plan");
   if (!d_dev || !n64) return fail(HFX_ERR_INVALID, "NULL argument");

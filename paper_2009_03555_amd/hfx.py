@@ -120,8 +120,10 @@ def lib():
         L.hfx_plan_destroy.argtypes = [vp]
         L.hfx_autotune.argtypes = [vp, vp, vp, ctypes.c_int64, ctypes.POINTER(hfx_tune_report)]
         L.hfx_screen_count.argtypes = [vp, vp, ctypes.POINTER(ctypes.c_int64), ctypes.POINTER(ctypes.c_int64)]
+        L.hfx_build_K_subset.argtypes = [vp, vp, vp, ctypes.POINTER(ctypes.c_uint64), ctypes.c_int64]
         for name in ("hfx_footprint", "hfx_plan", "hfx_pattern", "hfx_schwarz", "hfx_build_K",
-                     "hfx_build_K_multi", "hfx_export", "hfx_plan_destroy", "hfx_autotune", "hfx_screen_count"):
+                     "hfx_build_K_multi", "hfx_export", "hfx_plan_destroy", "hfx_autotune", "hfx_screen_count",
+                     "hfx_build_K_subset"):
             getattr(L, name).restype = ctypes.c_int
         _lib = L
     return _lib
@@ -219,6 +221,13 @@ class Plan:
         _check(lib().hfx_build_K(self._h, ctypes.c_void_p(_ptr(D)), ctypes.c_void_p(_ptr(K)), ctypes.c_uint32(flags),
                                  ctypes.byref(inf) if inf is not None else None))
         return inf.as_dict() if inf is not None else None
+
+    def build_K_subset(self, D, K, quartets: np.ndarray):
+        """``hfx_build_K_subset``: K from the given unique quartets only
+        (uint64 encoding of export(1))."""
+        q = np.ascontiguousarray(quartets, dtype=np.uint64)
+        _check(lib().hfx_build_K_subset(self._h, ctypes.c_void_p(_ptr(D)), ctypes.c_void_p(_ptr(K)),
+                                        q.ctypes.data_as(ctypes.POINTER(ctypes.c_uint64)), ctypes.c_int64(len(q))))
 
     def screen_count(self, D):
         """``hfx_screen_count``: (FP64-list, FP32-list) quartet counts for density D."""

@@ -64,3 +64,61 @@ def oracle_quartet_instances(rows):
 
 def key_set(keys):
     return set(map(tuple, np.asarray(keys).tolist()))
+
+
+def orbit_members(rows):
+    """Distinct ordered quartets of the orbits of the given ordered quartets
+    under the 8 index orders of the permutation relations, each translated
+    so that its first shell sits in the home cell.  rows: (n, 13) oracle
+    rows (I, J, N(3), K, L, M(3), G(3)), L at G + M.  Returns (m, 13)."""
+    inst = oracle_quartet_instances(rows)
+    out = set()
+    for q in inst:
+        for p in PERMS:
+            a = q[list(p)].copy()
+            a[:, 1:] -= a[0, 1:]
+            I, J, K, L = a[:, 0]
+            N, G, H = a[1, 1:], a[2, 1:], a[3, 1:]
+            out.add((int(I), int(J), *map(int, N), int(K), int(L), *map(int, H - G), *map(int, G)))
+    return np.array(sorted(out), dtype=np.int64).reshape(-1, 13)
+
+
+def gpu_rows(quartets, pairs):
+    """GPU list (n,5: bra, ket, G) + pair table -> oracle rows (n, 13)."""
+    inst = gpu_quartet_instances(quartets, pairs)
+    r = np.zeros((len(inst), 13), dtype=np.int64)
+    r[:, 0] = inst[:, 0, 0]
+    r[:, 1] = inst[:, 1, 0]
+    r[:, 2:5] = inst[:, 1, 1:]
+    r[:, 5] = inst[:, 2, 0]
+    r[:, 6] = inst[:, 3, 0]
+    r[:, 7:10] = inst[:, 3, 1:] - inst[:, 2, 1:]
+    r[:, 10:13] = inst[:, 2, 1:]
+    return r
+
+
+def to_gpu_quartets(rows, pairs, pair_class_of):
+    """One member of each ordered quartet's orbit in the device encoding
+    (bra pair | ket pair << 24 | translation << 48): the member whose bra
+    and ket pairs appear in the unique-pair table (A, B, n) in that
+    orientation, with class(bra) >= class(ket).  Returns uint64 array."""
+    index = {(int(a), int(b), int(n1), int(n2), int(n3)): i for i, (a, b, n1, n2, n3, _) in enumerate(pairs)}
+    out = []
+    for q in oracle_quartet_instances(rows):
+        found = None
+        for p in PERMS:
+            a = q[list(p)].copy()
+            a[:, 1:] -= a[0, 1:]
+            bra = index.get((int(a[0, 0]), int(a[1, 0]), *map(int, a[1, 1:])))
+            G = a[2, 1:]
+            ket = index.get((int(a[2, 0]), int(a[3, 0]), *map(int, a[3, 1:] - G)))
+            if bra is None or ket is None or pair_class_of[bra] < pair_class_of[ket]:
+                continue
+            if np.any(np.abs(G) > 15):
+                continue
+            g = int((G[0] + 16) | ((G[1] + 16) << 5) | ((G[2] + 16) << 10))
+            found = np.uint64(bra) | (np.uint64(ket) << np.uint64(24)) | (np.uint64(g) << np.uint64(48))
+            break
+        assert found is not None, "no member of the orbit in device orientation"
+        out.append(found)
+    return np.array(out, dtype=np.uint64)

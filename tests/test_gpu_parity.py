@@ -291,3 +291,54 @@ def test_kernel_override_rejects_unavailable(monkeypatch):
     monkeypatch.setenv("HFX_KERNELS", "55=reg")
     with pytest.raises(hfx.HfxError):
         hfx.Plan(_tiny_cell())
+
+
+# ------------------------------------------------ quartet subsets, full size
+def test_subset_of_whole_list_equals_build(cell):
+    q = cell.plan.export(1)
+    K = torch.full_like(cell.Dd, np.nan)
+    cell.plan.build_K_subset(cell.Dd, K, q)
+    assert np.max(np.abs(K.cpu().numpy() - cell.K)) <= 1e-13 * max(1.0, np.max(np.abs(cell.K)))
+    # any order, and the empty subset gives zero
+    K2 = torch.full_like(cell.Dd, np.nan)
+    cell.plan.build_K_subset(cell.Dd, K2, q[::-1].copy())
+    assert np.max(np.abs(K2.cpu().numpy() - cell.K)) <= 1e-13 * max(1.0, np.max(np.abs(cell.K)))
+    cell.plan.build_K_subset(cell.Dd, K2, q[:0])
+    assert torch.count_nonzero(K2).item() == 0
+
+
+def test_subset_rejects_bad_quartets(cell):
+    K = torch.zeros_like(cell.Dd)
+    with pytest.raises(hfx.HfxError):
+        cell.plan.build_K_subset(cell.Dd, K, np.array([np.uint64(1) << np.uint64(23)], dtype=np.uint64))
+
+
+def test_full_size_sampled_parity():
+    """The 64-atom periodic diamond workload of the benchmark at full size:
+    K from a seeded sample of quartets (drawn from the plain loop, one
+    member of each orbit in device orientation) on the GPU against the
+    oracle's plain terms of every member of the same orbits."""
+    from tests.helpers import canonical_keys, gpu_rows, oracle_quartet_instances, orbit_members, to_gpu_quartets
+    s = systems.config2_diamond()
+    plan = hfx.Plan(s)
+    o = oracle.Oracle(s)
+    D = _density(s, plan.blocks)
+    o.set_density(D)
+    rows = o.sample_quartets(240, seed=11)
+    keys = canonical_keys(oracle_quartet_instances(rows))
+    _, first = np.unique(keys, axis=0, return_index=True)
+    rows = rows[np.sort(first)]
+    pairs = plan.export(2)
+    q = to_gpu_quartets(rows, pairs, pairs[:, 5])
+    # the device representatives are members of the same orbits
+    rep = gpu_rows(hfx.unpack_quartets(q), pairs)
+    assert np.array_equal(canonical_keys(oracle_quartet_instances(rep)), canonical_keys(oracle_quartet_instances(rows)))
+    Dd = torch.from_numpy(D).to(DEV)
+    Kd = torch.full_like(Dd, np.nan)
+    plan.build_K_subset(Dd, Kd, q)
+    Kref, used = o.K_from_quartets(orbit_members(rows))
+    err = np.max(np.abs(Kd.cpu().numpy() - Kref))
+    print(f"full-size sample: {len(rows)} orbits, {used} ordered terms, max|dK| = {err:.3e}, "
+          f"max|K| = {np.max(np.abs(Kref)):.3e}")
+    assert used > len(rows)
+    assert err <= TOL_FP64

@@ -164,3 +164,23 @@ def test_periodic_equals_explicit_cluster(tiny_cell):
         assert np.allclose(_blk(oc, Kc, i), _blk(o, Ku, kp), rtol=0, atol=1e-12)
         checked += 1
     assert checked == len(o.blocks)
+
+
+def test_K_from_orbits_equals_plain_loop():
+    """The oracle's K from a given quartet set, fed every member of every
+    kept orbit, reproduces the plain screened loop (pins K_from_quartets for
+    the sampled full-size parity test)."""
+    from tests.helpers import canonical_keys, oracle_quartet_instances, orbit_members
+    for s in (systems.config1_molecule(seed=321),
+              systems.config2_diamond(seed=322, n=(1, 1, 1), nprim=1, shells=(0, 1), r_cut=4.0)):
+        o = oracle.Oracle(s)
+        o.schwarz()
+        o.set_density(o.density_from_system())
+        Kref, _ = o.build_K()
+        rows, _ = o.quartets(gR=2)
+        keys = canonical_keys(oracle_quartet_instances(rows))
+        _, first = np.unique(keys, axis=0, return_index=True)
+        members = orbit_members(rows[np.sort(first)])
+        assert len(members) == len(rows), "orbits of the kept quartets are exactly the kept quartets"
+        K, used = o.K_from_quartets(members)
+        assert np.max(np.abs(K - Kref)) <= 1e-12 * max(1.0, np.max(np.abs(Kref)))
