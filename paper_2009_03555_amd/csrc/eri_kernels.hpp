@@ -7,6 +7,17 @@
 
 namespace hfx {
 
+// Ket primitive iterations kept in flight by the one-lane kernel, per class:
+// two where measured faster (the unrolled loop needs more registers, which
+// costs occupancy in the other classes)
+constexpr int prim_unroll(int cb, int ck) {
+  const int r = region_of(cb, ck);
+  return (r == region_of(0, 0) || r == region_of(2, 0) || r == region_of(2, 2) || r == region_of(3, 1) ||
+          r == region_of(3, 2) || r == region_of(4, 0) || r == region_of(1, 1))
+             ? 2
+             : 1;
+}
+
 // ----------------------------------------------------------------- digest
 // The four "row-first" exchange contributions of one unique quartet
 // (A^0 B^nB | C^G D^(G+nD)) with weight w; K = K4 + K4^T is formed later.
@@ -128,7 +139,7 @@ __global__ __launch_bounds__(256) void eri_digest_kernel(const DevSys *__restric
     TV acct[C::NACC];
 #pragma unroll
     for (int k = 0; k < C::NACC; ++k) acct[k] = (TV)0;
-    prims += (unsigned long long)prim_sum<C, OP, TV>(s, s.pp + (int64_t)bpp.x * kPP, bpp.y,
+    prims += (unsigned long long)prim_sum<C, OP, TV, prim_unroll(CB, CK)>(s, s.pp + (int64_t)bpp.x * kPP, bpp.y,
                                                      s.pp + (int64_t)kpp.x * kPP, kpp.y, gx, gy, gz, 0, 1, acct,
                                                      prim_threshold(qb.pscr));
     double acc[C::NACC];

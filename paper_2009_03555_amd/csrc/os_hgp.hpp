@@ -281,7 +281,9 @@ __device__ __forceinline__ void hrr(const double *acc, const double *AB, const d
 // T is the type of the recursion and of the primitive sum: double, or float
 // for the mixed-precision path (the ladder, including the Boys function, and
 // the prefactor are always evaluated in double and rounded once).
-template <class C, int OP, typename T = double>
+// UNR: ket primitive iterations unrolled (2 keeps two in flight; measured
+// per class, see the one-lane kernel)
+template <class C, int OP, typename T = double, int UNR = 1>
 __device__ __forceinline__ int prim_sum(const DevSys &s, const double *__restrict__ ppb, int nb,
                                         const double *__restrict__ ppk, int nk, double gx, double gy,
                                         double gz, int lane, int stride, T *acc, double thr = 0.0) {
@@ -299,10 +301,23 @@ __device__ __forceinline__ int prim_sum(const DevSys &s, const double *__restric
     const double kb = b[7];
     const T o2z = (T)b[8];
     const double bthr = thr / b[9];
-    for (int ik = 0; ik < nk; ++ik) {
+    // kept ket pairs: a prefix (bisection on the descending bounds), so the
+    // loop below has a fixed trip count and two iterations can be in flight
+    int nke = 0;
+    {
+      int hi = nk;
+      while (nke < hi) {
+        const int mid = (nke + hi) >> 1;
+        if (ppk[(int64_t)mid * kPP + 9] < bthr)
+          hi = mid;
+        else
+          nke = mid + 1;
+      }
+    }
+    done += nke;
+#pragma unroll(UNR)
+    for (int ik = 0; ik < nke; ++ik) {
       const double *k = ppk + (int64_t)ik * kPP;
-      if (k[9] < bthr) break;
-      ++done;
       const double eta = k[0];
       const double Qx = k[1] + gx, Qy = k[2] + gy, Qz = k[3] + gz;
       const double ize = 1.0 / (zeta + eta);
