@@ -342,3 +342,16 @@ def test_full_size_sampled_parity():
           f"max|K| = {np.max(np.abs(Kref)):.3e}")
     assert used > len(rows)
     assert err <= TOL_FP64
+
+
+def test_max_primitives_and_angular_momentum():
+    """HFX_MAX_PRIM primitives on s, p and d shells (64 primitive pairs per
+    shell pair, the largest ragged primitive sets), Coulomb and erfc."""
+    for op in ("coulomb", "erfc"):
+        s = systems.random_cluster(2, 777, edge=4.0, min_sep=1.5, heavy=(0, 1, 2), light=(0, 1, 2), nprim=8,
+                                   op=op, omega=0.3)
+        c = Case(s)
+        Kref, _ = c.o.build_K()
+        err = np.max(np.abs(c.K - Kref))
+        print(f"8 primitives {op}: {c.info['n_quartets']} quartets, max|dK| = {err:.3e}")
+        assert err <= TOL_FP64
