@@ -315,7 +315,7 @@ __device__ __forceinline__ int prim_sum(const DevSys &s, const double *__restric
       }
     }
     done += nke;
-#pragma unroll(UNR)
+#pragma unroll UNR
     for (int ik = 0; ik < nke; ++ik) {
       const double *k = ppk + (int64_t)ik * kPP;
       const double eta = k[0];
