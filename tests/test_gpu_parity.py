@@ -355,3 +355,41 @@ def test_max_primitives_and_angular_momentum():
         err = np.max(np.abs(c.K - Kref))
         print(f"8 primitives {op}: {c.info['n_quartets']} quartets, max|dK| = {err:.3e}")
         assert err <= TOL_FP64
+
+
+@pytest.mark.parametrize("rep", [(2, 1, 1), (2, 2, 2)])
+def test_supercell_tiles_the_cell(rep):
+    """A supercell of the periodic cell computed as a cell, with the cell's
+    density tiled, gives the cell's K tiled (same pattern, same Q and P_max
+    per corresponding block, so the same screened terms)."""
+    kw = dict(seed=79, nprim=2, shells=(0, 1, 2), r_cut=4.6)
+    small = systems.config2_diamond(n=(1, 1, 1), **kw)
+    big = systems.config2_diamond(n=rep, **kw)
+    assert np.array_equal(small.prim_exp, big.prim_exp[: len(small.prim_exp)])
+    ps, pb = hfx.Plan(small), hfx.Plan(big)
+    nsh = 3                                      # shells per atom
+    Ds = _density(small, ps.blocks)
+    skey = {tuple(int(v) for v in b): i for i, b in enumerate(ps.blocks)}
+    reps = np.array(rep)
+
+    def cellvec(shell):
+        c = (shell // nsh) // 8                  # conventional cell of the atom
+        return np.array([c // (rep[1] * rep[2]), (c // rep[2]) % rep[1], c % rep[2]])
+
+    def small_shell(shell):
+        return ((shell // nsh) % 8) * nsh + shell % nsh
+
+    mapped = []
+    for (I, J, n1, n2, n3) in pb.blocks:
+        m = cellvec(J) - cellvec(I) + np.array([n1, n2, n3]) * reps
+        mapped.append(skey[(small_shell(I), small_shell(J), *map(int, m))])
+    Db = np.concatenate([Ds[ps.offsets[b]:ps.offsets[b + 1]] for b in mapped])
+    Ks = torch.zeros(ps.nnz, dtype=torch.float64, device=DEV)
+    Kb = torch.zeros(pb.nnz, dtype=torch.float64, device=DEV)
+    ps.build_K(torch.from_numpy(Ds).to(DEV), Ks, flags=hfx.HFX_SYNC)
+    pb.build_K(torch.from_numpy(Db).to(DEV), Kb, flags=hfx.HFX_SYNC)
+    Ks, Kb = Ks.cpu().numpy(), Kb.cpu().numpy()
+    Kt = np.concatenate([Ks[ps.offsets[b]:ps.offsets[b + 1]] for b in mapped])
+    err = np.max(np.abs(Kb - Kt))
+    print(f"supercell {rep}: {len(pb.blocks)} blocks, max|dK| = {err:.3e}")
+    assert err <= 1e-12 * max(1.0, np.max(np.abs(Ks)))
