@@ -89,7 +89,9 @@ typedef struct {
   double omega;               /* bohr^-1, used iff op == HFX_OP_ERFC */
   double tau;                 /* keep a quartet iff bound > tau (>= 0) */
   int32_t precision;          /* hfx_precision */
-  double fp32_cutoff;         /* HFX_MIXED: Q_IJ*Q_KL below this -> FP32 path */
+  double fp32_cutoff;         /* HFX_MIXED: Q_IJ*Q_KL below this allows the FP32 path;
+                                 classes whose FP32 kernel is no faster stay FP64:
+                                 (ss|ss) (ps|ss) (ps|ps) (pp|ps) (ds|ss) (dd|ss) */
   int32_t spherical_d;        /* 1: five spherical d functions; 0: six Cartesian */
 } hfx_system;
 

@@ -36,9 +36,12 @@ struct LaneShape {
   static constexpr int NGRP = 64 / NS;
   static constexpr int NGT = noff(LG + 1) - noff(GL);
   // read a whole level's coupling operands at once: measured faster where
-  // the registers allow it (grow side up to L = 3, and (dd|dd), which runs
-  // one wave per SIMD either way)
-  static constexpr bool kBatchReads = LG <= 3 || (CB == 5 && CK == 5);
+  // the registers allow it (grow side up to L = 3, (dd|dd), which runs one
+  // wave per SIMD either way, and every FP32 kernel)
+  template <typename TV>
+  static constexpr bool batch_reads() {
+    return LG <= 3 || (CB == 5 && CK == 5) || sizeof(TV) == 4;
+  }
   static constexpr int NE = noff(EB + 1) - noff(LA), NF = noff(FK + 1) - noff(LC);
   static constexpr int NA = ncart(LA), NB = ncart(LB), NC = ncart(LC), ND = ncart(LD);
   // primitive quartets staged per batch, a multiple of the group count:
@@ -89,15 +92,21 @@ __device__ __forceinline__ void wave_lds_sync() {
 
 // The electron-coupling operands cross lanes through LDS: each level is
 // published and read back (register shuffles measured slower)
-// two waves per SIMD wanted: the register budget is then 256 per lane; the
-// (dd|dd) kernel needs more and runs one wave per SIMD
-template <int CB, int CK>
+// FP64: two waves per SIMD wanted, a register budget of 256 per lane; the
+// (dd|dd) kernel needs more and runs one wave per SIMD.  FP32: three waves
+// for (dp|dp), (dd|pp), (dd|ds) (measured 2-14% faster despite a few spilled
+// registers); elsewhere three cost more than they gain, or the kernel gets
+// there by itself
+template <int CB, int CK, typename TV>
 constexpr int lane_waves() {
+  if constexpr (sizeof(TV) == 4) {
+    if ((CB == 4 && CK == 4) || (CB == 5 && (CK == 2 || CK == 3))) return 3;
+  }
   return (CB == 5 && CK == 5) ? 1 : 2;
 }
 
 template <int CB, int CK, int OP, bool KL, typename TV>
-__global__ __attribute__((amdgpu_flat_work_group_size(64, 64), amdgpu_waves_per_eu(lane_waves<CB, CK>())))
+__global__ __attribute__((amdgpu_flat_work_group_size(64, 64), amdgpu_waves_per_eu(lane_waves<CB, CK, TV>())))
 void eri_lane_kernel(const DevSys *__restrict__ sys, int nsys,
                                                       const int64_t *__restrict__ seg, CoopDev cd,
                                                       const uint64_t *__restrict__ list,
@@ -252,7 +261,7 @@ void eri_lane_kernel(const DevSys *__restrict__ sys, int nsys,
           constexpr int lv = decltype(lv_)::value;
           constexpr int MR = LG - lv;
           constexpr int rb = ((lv - 1) & 1) * PBL, wb = (lv & 1) * PBL;
-          if constexpr (SH::kBatchReads) {
+          if constexpr (SH::template batch_reads<TV>()) {
             // every electron-coupling operand of the level first (one
             // wait), the lane-local terms while they arrive, then the
             // coupling terms

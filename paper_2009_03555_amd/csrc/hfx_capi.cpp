@@ -500,9 +500,20 @@ bool variant_available(int cb, int ck, int v) {
 }
 bool variant_fp32(int v) { return v == K_REG32 || v == K_LANE32; }
 
-// FP32-list kernel that goes with FP64-list kernel k64
+// Classes whose one-lane kernel gains nothing from the FP32 recursion
+// (measured on the 64-atom diamond recipe: (ss|ss), (ps|ss), (ps|ps), (pp|ps),
+// (ds|ss), (dd|ss) are Boys- and latency-bound, FP32 within 1% or slower);
+// their quartets stay on the FP64 list, which also saves a launch.
+bool fp32_gains(int cb, int ck) {
+  const int r = region_of(cb, ck);
+  return !(r == region_of(0, 0) || r == region_of(1, 0) || r == region_of(1, 1) || r == region_of(2, 1) ||
+           r == region_of(3, 0) || r == region_of(5, 0));
+}
+
+// FP32-list kernel that goes with FP64-list kernel k64 (an FP64 variant:
+// the class does not split, see fp32_gains)
 int default_kern32(int cb, int ck, int k64) {
-  if (k64 == K_REG && variant_available(cb, ck, K_REG32)) return K_REG32;
+  if (k64 == K_REG && variant_available(cb, ck, K_REG32) && fp32_gains(cb, ck)) return K_REG32;
   if (k64 == K_LANE) return K_LANE32;
   return k64;
 }
@@ -643,7 +654,10 @@ hfx_status upload_plan(hfx_plan_s &P) {
   s.op = P.op;
   s.omega2 = P.omega * P.omega;
   s.tau = P.tau;
-  s.fp32_cutoff = P.precision == HFX_MIXED ? P.fp32_cutoff : 0.0;
+  // a class takes the FP32 list only if its FP32-list kernel is an FP32
+  // variant (the default, an HFX_KERNELS choice)
+  for (int r = 0; r < kNQuartetClass; ++r)
+    s.fp32_cut[r] = (P.precision == HFX_MIXED && variant_fp32(P.kern32[r])) ? P.fp32_cutoff : 0.0;
   s.boys = P.d_boys;
   s.Dc = P.d_Dc;
   s.K4 = P.d_K4;

@@ -141,7 +141,9 @@ struct DevSys {
   int32_t op;             // 0 Coulomb, 1 erfc
   double omega2;
   double tau;
-  double fp32_cutoff;     // mixed precision: Q_IJ*Q_KL below this -> FP32 recursion
+  // mixed precision, per class region: quartets with Q_IJ*Q_KL below this
+  // go to the FP32 list (0: the class stays on the FP64 list)
+  double fp32_cut[kNQuartetClass];
   const double *boys;     // kBoysRows x kBoysCols
   // per-build state of this plan
   const double *Dc;       // Cartesian density blocks

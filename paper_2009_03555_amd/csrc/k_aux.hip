@@ -292,11 +292,11 @@ __device__ __forceinline__ double pmax_at(const DevSys &s, int I, int J, int a, 
 // visited: (p|p^G) and (p|p^-G) are one orbit of the permutation relations.
 template <typename F>
 __device__ __forceinline__ void visit_kept(const DevSys &s, int p, int q, double Qp, double Qq, double pglob,
-                                           int mode, int32_t *err, F &&emit) {
+                                           int mode, double cut32, int32_t *err, F &&emit) {
   const double qq = Qp * Qq;
   if (!(qq * pglob > s.tau)) return;
-  if (mode == 1 && !(qq >= s.fp32_cutoff)) return;
-  if (mode == 2 && !(qq < s.fp32_cutoff)) return;
+  if (mode == 1 && !(qq >= cut32)) return;
+  if (mode == 2 && !(qq < cut32)) return;
   const int4 bi = s.pr_info[p], ki = s.pr_info[q];
   int nB1, nB2, nB3, nD1, nD2, nD3;
   unpack_img8(bi.z, nB1, nB2, nB3);
@@ -362,6 +362,7 @@ __global__ __launch_bounds__(256) void screen_kernel(const DevSys *__restrict__ 
   const int q0 = class_start[ck];
   const int q1 = (cb == ck) ? p + 1 : class_start[ck + 1];
   const double Qp = s.pr_Q[p];
+  const double cut32 = s.fp32_cut[r];
   const double pglob = __longlong_as_double((long long)*s.pmax_global);
   int64_t running = fill ? offsets[item] : 0;
   for (int qt = q0; qt < q1; qt += 64) {
@@ -370,7 +371,7 @@ __global__ __launch_bounds__(256) void screen_kernel(const DevSys *__restrict__ 
     double Qq = 0.0;
     if (q < q1) {
       Qq = s.pr_Q[q];
-      visit_kept(s, p, q, Qp, Qq, pglob, mode, err, [&](int, int, int) { ++cnt; });
+      visit_kept(s, p, q, Qp, Qq, pglob, mode, cut32, err, [&](int, int, int) { ++cnt; });
     }
     // wave-wide inclusive scan of cnt
     int x = cnt;
@@ -382,7 +383,7 @@ __global__ __launch_bounds__(256) void screen_kernel(const DevSys *__restrict__ 
     const int total = __shfl(x, 63, 64);
     if (fill && q < q1 && cnt) {
       int64_t pos = running + (x - cnt);
-      visit_kept(s, p, q, Qp, Qq, pglob, mode, err, [&](int g1, int g2, int g3) {
+      visit_kept(s, p, q, Qp, Qq, pglob, mode, cut32, err, [&](int g1, int g2, int g3) {
         if (pos < cap)
           out[pos] = pack_quartet((uint32_t)p, (uint32_t)q, pack_img5(g1, g2, g3));
         else

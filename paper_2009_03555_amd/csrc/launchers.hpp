@@ -97,12 +97,11 @@ void launch_finalize(const DevSys &s, int64_t nblk, const int2 *blk_IJ, const in
                      const int32_t *partner, int spherical, const double *K4, double *K, hipStream_t st);
 void launch_zero(double *p, int64_t n, hipStream_t st);
 void launch_zero_u64(unsigned long long *p, int64_t n, hipStream_t st);
-// Screening: one wave per item (region, bra pair).  count pass writes
-// counts[item]; fill pass writes the quartets at offsets[item].
-// Screening over fused work items (region, bra pair, plan).  mode: 0 every
-// kept quartet, 1 only Q_IJ*Q_KL >= fp32_cutoff (FP64 path), 2 only
-// Q_IJ*Q_KL < fp32_cutoff (FP32 path).  Count pass writes counts[item]; fill
-// pass writes at offsets[item] and never at or beyond cap (sets err bit 2).
+// Screening over fused work items (region, bra pair, plan), one wave per
+// item.  mode: 0 every kept quartet, 1 only Q_IJ*Q_KL >= the region's
+// fp32_cut (FP64 list), 2 only Q_IJ*Q_KL < fp32_cut (FP32 list).  Count pass
+// writes counts[item]; fill pass writes at offsets[item] and never at or
+// beyond cap (sets err bit 2).
 void launch_screen(const DevSys *sys, const int4 *items, int64_t nitems, int32_t *counts, const int64_t *offsets,
                    uint64_t *out, int64_t cap, int32_t *err, bool fill, int mode, hipStream_t st);
 // seg[k] = min(offsets[seg_items[k]], cap), k < n: class-segment bounds on

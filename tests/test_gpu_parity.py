@@ -233,19 +233,31 @@ def test_mixed_precision_periodic_erfc(cutoff):
     # the two lists together are the FP64 list
     both = np.concatenate([pmx.export(1), pmx.export(5)])
     assert np.array_equal(np.sort(both), np.sort(p64.export(1)))
+    # classes whose FP32 kernel is no faster keep every quartet on the FP64 list
+    cls = pmx.export(2)[:, 5]
+    q32 = pmx.export(5)
+    bra_c = cls[(q32 & 0xFFFFFF).astype(np.int64)]
+    ket_c = cls[((q32 >> 24) & 0xFFFFFF).astype(np.int64)]
+    fp64_only = {(0, 0), (1, 0), (1, 1), (2, 1), (3, 0), (5, 0)}
+    assert not any((max(int(b), int(k)), min(int(b), int(k))) in fp64_only for b, k in zip(bra_c, ket_c))
+    assert len(q32) == imx["n_fp32_quartets"]
 
 
-def test_mixed_precision_cluster_config3_recipe():
-    # small enough for the oracle: 5 atoms (3 heavy, 2 light), 3 primitives
+@pytest.mark.parametrize("cutoff", [1e-6, 1e-3])
+def test_mixed_precision_cluster_config3_recipe(cutoff):
+    # small enough for the oracle: 5 atoms (3 heavy, 2 light), 3 primitives.
+    # At the recipe's 1e-6 this cluster's quartets below the cutoff all fall
+    # in classes that stay FP64; 1e-3 puts d-shell classes on the FP32 list.
     s = systems.random_cluster(5, 2024, nprim=3, op="coulomb", tau=1e-10, precision="mixed",
-                               fp32_cutoff=1e-6)
+                               fp32_cutoff=cutoff)
     plan, D, K, info = _build(s)
     o = oracle.Oracle(s)
     o.set_density(D)
     Kref, _ = o.build_K()
     err = np.max(np.abs(K - Kref))
-    print(f"cluster5 mixed: {info['n_fp32_quartets']}/{info['n_quartets']} FP32, max|dK| {err:.2e}")
-    assert info["n_fp32_quartets"] > 0
+    print(f"cluster5 mixed {cutoff}: {info['n_fp32_quartets']}/{info['n_quartets']} FP32, max|dK| {err:.2e}")
+    if cutoff > 1e-6:
+        assert info["n_fp32_quartets"] > 0
     assert err <= TOL_MIXED
 
 
