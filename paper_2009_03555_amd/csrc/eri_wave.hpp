@@ -31,8 +31,12 @@ __device__ __forceinline__ double lds(const char *base, uint32_t byte_off) {
 //   15..17   Q - C        18..20  W - Q
 //   21 1/(2 zeta)  22 rho/zeta  23 1/(2 eta)  24 rho/eta  25 1/(2 (zeta + eta))
 //   26 1.0  27 0.0 (coefficients of an identity step)
+// The row stride is odd (29 doubles): rows written by consecutive lanes, and
+// the rows different lane groups read at once, then fall in different LDS
+// banks (an even stride of 28 left 2- to 16-way bank conflicts; measured 4%
+// faster on the six-group lane kernels).
 constexpr int kCoopBatch = 16;  // batch of the cooperative kernel
-constexpr int kCoopStage = 28;
+constexpr int kCoopStage = 29;
 // LDS ints for the prefix sums of a ragged primitive-quartet set (<= 64 + 1)
 constexpr int kPfxInts = kMaxPrim * kMaxPrim + 2;
 
