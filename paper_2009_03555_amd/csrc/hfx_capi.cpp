@@ -617,10 +617,11 @@ hfx_status upload_plan(hfx_plan_s &P) {
     for (int ck = 0; ck <= cb; ++ck) {
       const int r = region_of(cb, ck);
       // the lane kernel where the one-lane recursion spills or is absent
-      // (bra dp or dd with a ket of two or more angular momentum units);
-      // elsewhere the one-lane kernel, measured faster (the autotuner
-      // revisits the choice per plan)
-      const bool heavy = cb >= 4 && class_la(ck) + class_lb(ck) >= 2;
+      // (bra dp or dd with a ket of two or more angular momentum units,
+      // except (dp|ds): 96 accumulators, its one-lane kernel measured 37%
+      // faster on the 64-atom diamond cell); elsewhere the one-lane kernel,
+      // measured faster (the autotuner revisits the choice per plan)
+      const bool heavy = cb >= 4 && class_la(ck) + class_lb(ck) >= 2 && !(cb == 4 && ck == 3);
       P.kern[r] = (heavy || !register_available(cb, ck)) ? K_LANE : K_REG;
       P.kern32[r] = default_kern32(cb, ck, P.kern[r]);
     }
