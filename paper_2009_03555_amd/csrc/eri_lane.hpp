@@ -45,9 +45,11 @@ struct LaneShape {
   static constexpr int NE = noff(EB + 1) - noff(LA), NF = noff(FK + 1) - noff(LC);
   static constexpr int NA = ncart(LA), NB = ncart(LB), NC = ncart(LC), ND = ncart(LD);
   // primitive quartets staged per batch, a multiple of the group count:
-  // about 32, or 60 for six groups with a grow side up to L = 3 (measured:
-  // 8% faster there, slower elsewhere through the larger LDS footprint)
-  static constexpr int NBATCH = (NGRP == 6 && LG <= 3) ? 60 : NGRP * ((32 + NGRP - 1) / NGRP);
+  // about 32, or 60 for six groups with a grow side up to L = 3 and for
+  // (dp|dp) (measured 8% and 5% faster there; elsewhere the larger LDS
+  // footprint costs waves per CU)
+  static constexpr int NBATCH =
+      ((NGRP == 6 && LG <= 3) || (CB == 4 && CK == 4)) ? 60 : NGRP * ((32 + NGRP - 1) / NGRP);
   // register slots V[lv][c][m], m = 0..LG-lv
   __host__ __device__ static constexpr int vw(int lv) { return LG - lv + 1; }
   __host__ __device__ static constexpr int vo(int lv, int c, int m) {

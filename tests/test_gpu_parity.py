@@ -280,6 +280,8 @@ def test_kernel_variants_match_oracle(variant, cell, monkeypatch):
     err = np.max(np.abs(Kd.cpu().numpy() - Kref))
     print(f"{variant}: max|dK| = {err:.3e}")
     assert info["n_quartets"] == cell.info["n_quartets"]
+    # every kernel applies the same primitive-quartet test (B_ket < thr / B_bra)
+    assert info["n_prim_quartets"] == cell.info["n_prim_quartets"]
     assert err <= TOL_FP64
 
 
