@@ -45,11 +45,15 @@ struct LaneShape {
   static constexpr int NE = noff(EB + 1) - noff(LA), NF = noff(FK + 1) - noff(LC);
   static constexpr int NA = ncart(LA), NB = ncart(LB), NC = ncart(LC), ND = ncart(LD);
   // primitive quartets staged per batch, a multiple of the group count:
-  // about 32, or 60 for six groups with a grow side up to L = 3 and for
-  // (dp|dp) (measured 8% and 5% faster there; elsewhere the larger LDS
-  // footprint costs waves per CU)
-  static constexpr int NBATCH =
-      ((NGRP == 6 && LG <= 3) || (CB == 4 && CK == 4)) ? 60 : NGRP * ((32 + NGRP - 1) / NGRP);
+  // about 32, or 60 for six groups with a grow side up to L = 3 and for the
+  // FP64 (dp|dp) kernel (measured 8% and 5% faster there; elsewhere the
+  // larger LDS footprint costs waves per CU, as it would for the FP32
+  // (dp|dp) kernel, which runs three waves per SIMD)
+  template <typename TV>
+  static constexpr int nbatch() {
+    return ((NGRP == 6 && LG <= 3) || (sizeof(TV) == 8 && CB == 4 && CK == 4)) ? 60
+                                                                              : NGRP * ((32 + NGRP - 1) / NGRP);
+  }
   // register slots V[lv][c][m], m = 0..LG-lv
   __host__ __device__ static constexpr int vw(int lv) { return LG - lv + 1; }
   __host__ __device__ static constexpr int vo(int lv, int c, int m) {
@@ -79,7 +83,7 @@ struct LaneShape {
   }
   template <typename TV>
   __host__ __device__ static constexpr size_t lds_bytes() {
-    return (size_t)(work_doubles<TV>() + NBATCH * kCoopStage) * sizeof(double) + kPfxInts * sizeof(int);
+    return (size_t)(work_doubles<TV>() + nbatch<TV>() * kCoopStage) * sizeof(double) + kPfxInts * sizeof(int);
   }
 };
 
@@ -115,7 +119,7 @@ void eri_lane_kernel(const DevSys *__restrict__ sys, int nsys,
                                                       unsigned long long *__restrict__ nprim) {
   using SH = LaneShape<CB, CK, KL>;
   constexpr int L = SH::L, LS = SH::LS, LG = SH::LG, GL = SH::GL, NS = SH::NS, NGRP = SH::NGRP;
-  constexpr int NGT = SH::NGT, NF = SH::NF, PBL = SH::pbl(), NBATCH = SH::NBATCH;
+  constexpr int NGT = SH::NGT, NF = SH::NF, PBL = SH::pbl(), NBATCH = SH::template nbatch<TV>();
   // stage slots of the lane side and of the grow side
   constexpr int XS = KL ? 15 : 9, YS = KL ? 18 : 12, OS2 = KL ? 23 : 21, RS = KL ? 24 : 22;
   constexpr int XG = KL ? 9 : 15, YG = KL ? 12 : 18, OG2 = KL ? 21 : 23, RG = KL ? 22 : 24;
