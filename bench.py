@@ -274,6 +274,8 @@ def main():
 
     prec = "fp64" if args.precision in ("fp64", "both") else "mixed"
     s = workload(args.workload, prec)
+    if prec == "mixed":
+        s = s.with_(fp32_cutoff=args.fp32_cutoff, name=s.name)
     plan = hfx.Plan(s)
     D = np.concatenate([v.ravel() for v in systems.density_blocks(s, plan.blocks.astype(np.int64))])
     Dd = torch.from_numpy(D).cuda()
@@ -318,6 +320,7 @@ def main():
         "config": {"workload": s.name, "n_atoms": s.n_atoms, "n_shells": s.n_shells,
                    "n_basis": s.n_functions(), "periodic": s.periodic, "op": s.op, "omega": s.omega,
                    "pair_cutoff": s.pair_cutoff, "tau": s.tau, "precision": prec,
+                   **({"fp32_cutoff": s.fp32_cutoff} if prec == "mixed" else {}),
                    "n_blocks": plan.n_blocks, "nnz": plan.nnz},
         "builds_per_s": args.steps / total,
         "latency_ms_p50": float(np.percentile(lat, 50) * 1e3),
