@@ -1174,7 +1174,7 @@ void drop_graphs_of(const hfx_plan_s *P) {
 }
 
 // grid caps tried per kernel family (0 = default)
-const int64_t kTuneGridReg[] = {0, 256 * 4, 256 * 16};
+const int64_t kTuneGridReg[] = {0, 256 * 16, 256 * 64};  // one-wave blocks: 262k and 1M threads
 const int64_t kTuneGridWave[] = {0, 256 * 8, 256 * 64};
 
 hfx_status tune_class(Batch &B, int cb, int ck, bool f32, int64_t max_q, int64_t *d_seg2, hfx_tune_report *rep) {
