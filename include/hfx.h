@@ -136,7 +136,8 @@ hfx_status hfx_pattern(hfx_plan_t plan, int64_t *n_blocks, int64_t *nnz, const h
  * n_blocks doubles to receive them.  *n_pairs: number of unique pairs. */
 hfx_status hfx_schwarz(hfx_plan_t plan, double *q_host, int64_t *n_pairs);
 
-/* One exchange build (Eq. H-HFX with the screening of Eq. screen):
+/* One exchange build (Eq. H-HFX with the screening of Eq. schwarz and
+ * Eq. dmscreening):
  * d_dev, k_dev are device arrays of nnz doubles in the pattern layout
  * (caller-owned).  K is overwritten.  Runs hfx_schwarz first if it has not
  * run.  Asynchronous on the plan's stream unless HFX_SYNC, HFX_TIMING or
