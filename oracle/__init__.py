@@ -65,6 +65,8 @@ def lib():
         L.oracle_block_offsets.argtypes = [ctypes.c_void_p, i64p]
         L.oracle_schwarz.argtypes = [ctypes.c_void_p, dp]
         L.oracle_set_density.argtypes = [ctypes.c_void_p, dp, dp]
+        L.oracle_density_cart.restype = ctypes.c_int64
+        L.oracle_density_cart.argtypes = [ctypes.c_void_p, i64p, dp]
         L.oracle_build_K.restype = ctypes.c_int64
         L.oracle_build_K.argtypes = [ctypes.c_void_p, ctypes.c_int64, i64p, ctypes.c_int, dp]
         L.oracle_quartets.restype = ctypes.c_int64
@@ -185,6 +187,16 @@ class Oracle:
         self.Pmax = np.zeros(len(self.blocks))
         lib().oracle_set_density(self.h, _p(d), _p(self.Pmax))
         return self.Pmax
+
+    def density_cart(self):
+        """Cartesian density blocks of the last set_density: (block offsets
+        [n_blocks + 1], values [nnz_cart]); block b is ncart(I) x ncart(J)
+        row-major at offsets[b]."""
+        n = lib().oracle_density_cart(self.h, None, None)
+        coff = np.zeros(len(self.blocks) + 1, dtype=np.int64)
+        dc = np.zeros(max(n, 1))
+        lib().oracle_density_cart(self.h, _p(coff, ctypes.c_int64), _p(dc))
+        return coff, dc[:n]
 
     def density_from_system(self, iteration: int = 0) -> np.ndarray:
         from systems import density_blocks

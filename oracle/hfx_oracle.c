@@ -566,6 +566,16 @@ void oracle_set_density(void *h, const double *d, double *pmax_out) {
   if (pmax_out) memcpy(pmax_out, s->Pmax, sizeof(double) * s->nblk);
 }
 
+/* Cartesian density of the last oracle_set_density, for checking it:
+ * coff_out[nblk + 1] block offsets, dc_out[nnz_c] values (either may be
+ * NULL); returns nnz_c. */
+int64_t oracle_density_cart(void *h, int64_t *coff_out, double *dc_out) {
+  osys *s = (osys *)h;
+  if (coff_out) memcpy(coff_out, s->blk_coff, sizeof(int64_t) * (s->nblk + 1));
+  if (dc_out) memcpy(dc_out, s->Dc, sizeof(double) * s->nnz_c);
+  return s->nnz_c;
+}
+
 static double pm(const osys *s, int I, int J, int n1, int n2, int n3) {
   int64_t b = find_block(s, I, J, n1, n2, n3);
   return b < 0 ? 0.0 : s->Pmax[b];

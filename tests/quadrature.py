@@ -57,3 +57,39 @@ def cart_powers(l):
         for y in range(l - x, -1, -1):
             out.append((x, y, l - x - y))
     return out
+
+
+def uquad_eri_fast(A, B, C, D, a, b, c, d, pa, pb, pc, pd, u0=0.0, scale=1.0):
+    """``uquad_eri`` with every u node at once (same rules, same result to
+    rounding): the 2x2 Cholesky factor and solve are written out so that all
+    nodes are evaluated as arrays."""
+    th = (_GL_X + 1) / 2
+    wt = _GL_W / 2
+    u = u0 + scale * np.tan(np.pi * th / 2)
+    du = scale * np.pi / 2 / np.cos(np.pi * th / 2) ** 2
+    u2 = u * u
+    p = a + b
+    q = c + d
+    m11, m12, m22 = p + u2, -u2, q + u2
+    l11 = np.sqrt(m11)
+    l21 = m12 / l11
+    l22 = np.sqrt(m22 - l21 * l21)
+    det_m = m11 * m22 - m12 * m12
+    w1 = _GH_X[:, None]
+    w2 = _GH_X[None, :]
+    WW = np.outer(_GH_W, _GH_W)
+    f = np.ones_like(u)
+    for k in range(3):
+        v1 = a * A[k] + b * B[k]
+        v2 = c * C[k] + d * D[k]
+        const = a * A[k] ** 2 + b * B[k] ** 2 + c * C[k] ** 2 + d * D[k] ** 2
+        mu1 = (m22 * v1 - m12 * v2) / det_m
+        mu2 = (m11 * v2 - m12 * v1) / det_m
+        # z = mu + L^-T w, L^-T = [[1/l11, -l21/(l11 l22)], [0, 1/l22]]
+        x = mu1[:, None, None] + w1[None] / l11[:, None, None] - (l21 / (l11 * l22))[:, None, None] * w2[None]
+        xp = mu2[:, None, None] + w2[None] / l22[:, None, None]
+        poly = (x - A[k]) ** pa[k] * (x - B[k]) ** pb[k] * (xp - C[k]) ** pc[k] * (xp - D[k]) ** pd[k]
+        quad = np.sum(WW[None] * poly, axis=(1, 2))
+        expo = mu1 * (m11 * mu1 + m12 * mu2) + mu2 * (m12 * mu1 + m22 * mu2) - const
+        f = f * quad / (l11 * l22) * np.exp(expo)
+    return 2.0 / np.sqrt(np.pi) * np.sum(wt * du * f)
