@@ -113,13 +113,18 @@ typedef struct {
   int64_t n_fp32_quartets;                /* quartets taken on the FP32 path */
   double flops;                           /* algorithmic FLOPs of the ERI phase */
   double ms_density, ms_screen, ms_eri, ms_finalize, ms_total; /* HFX_TIMING */
-  double ms_class[HFX_N_CLASSES];         /* HFX_TIMING: ERI kernel time per class */
+  double ms_class[HFX_N_CLASSES];         /* HFX_TIMING: ERI kernel time per class (0 for a
+                                             chunked list, whose ERI time counts in ms_screen) */
   double flops_class[HFX_N_CLASSES];      /* algorithmic FLOPs per class */
+  int64_t n_chunks;                       /* list chunks evaluated (0: every list whole) */
 } hfx_build_info;
 
-/* Device bytes hfx_plan would allocate for this system, excluding the
- * per-build quartet list (reported separately in *list_bytes_per_quartet).
- * Validates like hfx_plan; allocates nothing on the device. */
+/* Device bytes hfx_plan would allocate for this system (its tables and its
+ * own one-plan batch), plus the plan's share of a fused multi-plan batch,
+ * excluding the per-build quartet lists (8 bytes per screened quartet,
+ * reported in *list_bytes_per_quartet) and the second-spin arrays of
+ * hfx_build_K_spin.  Validates like hfx_plan; allocates nothing on the
+ * device. */
 hfx_status hfx_footprint(const hfx_system *sys, size_t *device_bytes, size_t *list_bytes_per_quartet);
 
 /* Validate, normalise contractions, build the pattern, shell-pair and
@@ -152,6 +157,56 @@ hfx_status hfx_schwarz(hfx_plan_t plan, double *q_host, int64_t *n_pairs);
  * HFX_TIMING takes precedence over HFX_GRAPH. */
 hfx_status hfx_build_K(hfx_plan_t plan, const double *d_dev, double *k_dev, uint32_t flags,
                        hfx_build_info *info);
+
+/* Collinear spin: the exchange matrix of each spin density,
+ * K^s_{mu nu} = sum_{lambda sigma} (mu lambda|nu sigma) D^s_{lambda sigma},
+ * s = alpha, beta - Eq. H-HFX applied per spin, the spin-polarised form of
+ * the Kohn-Sham equations the Background section writes for the
+ * unpolarised case.  Every unique quartet's integrals are evaluated once and
+ * digested into both K's.  One quartet list serves both spins: P_max of a
+ * block is the larger of the two densities' block maxima (Eq. dmscreening
+ * over both spins), so each K^s keeps every term a separate build of D^s
+ * keeps, and possibly a few more of bound at most tau.  D and K arrays as
+ * for hfx_build_K (caller-owned, nnz doubles each); flags and info as for
+ * hfx_build_K (info: counts of the shared evaluation; flops include both
+ * digests).  The first call allocates the plan's second-spin arrays. */
+hfx_status hfx_build_K_spin(hfx_plan_t plan, const double *d_alpha, const double *d_beta, double *k_alpha,
+                            double *k_beta, uint32_t flags, hfx_build_info *info);
+
+/* Hartree-Fock exchange part of the Hamiltonian at k-points, from the
+ * real-space exchange matrix of a build (Background section: the Bloch sum
+ * of the Hamiltonian, [H(k)]_{mu nu} = sum_R <chi_mu^0|H|chi_nu^R>
+ * exp(i k.(R + r_nu - r_mu)), applied to Eq. H-HFX, whose HFX part carries
+ * the factor -1/2; alpha is the fraction of exact exchange the functional
+ * mixes in, 1/4 for HSE06 (its short-range HF term, with the erfc
+ * operator), 1 for Hartree-Fock):
+ *   H(k)_{mu nu} = -(alpha / 2) sum_G K^G_{mu nu} exp(i k.(T_G + r_nu - r_mu)),
+ * r_mu the home-cell position of mu's atom, T_G the lattice vector of
+ * pattern block (mu's shell, nu's shell, G).
+ * k_dev: device array of nnz doubles, K in the pattern layout (as written by
+ * hfx_build_K).  kpts_host: host array [nk][3] of Cartesian k-points
+ * (bohr^-1).  h_dev: caller-owned device array of 2 * nk * nbf * nbf
+ * doubles, written as nk dense complex matrices (real, imaginary
+ * interleaved), row-major, rows and columns in the boundary basis of the
+ * cell's functions (shell order; nbf = their number); entries of shell
+ * pairs outside the pattern are zero.  A molecule has T_G = 0 (use k = 0).
+ * Runs on the plan's stream and synchronises it before returning. */
+hfx_status hfx_kspace(hfx_plan_t plan, const double *k_dev, int32_t nk, const double *kpts_host, double alpha,
+                      double *h_dev);
+
+/* Largest number of unique quartets a build of this plan holds in one
+ * quartet list (8 bytes each; default 2^31, i.e. 16 GiB; 0 restores the
+ * default).  A screened list longer than this is evaluated in chunks: the
+ * screening work items (one bra pair against one ket class) are cut into
+ * consecutive ranges whose quartets fit, and each range is filled and run
+ * through the ERI kernels before the next overwrites the buffer - the
+ * batched evaluation of Algorithm 4 on one device.  Results equal the
+ * unchunked build up to the order of floating-point additions.  A single
+ * work item larger than the limit fails with HFX_ERR_OOM.  Chunked builds
+ * run eagerly (no HFX_GRAPH replay) and keep no whole list for hfx_export
+ * or hfx_autotune.  Fused multi-plan builds use the smallest limit of their
+ * plans. */
+hfx_status hfx_set_list_limit(hfx_plan_t plan, int64_t max_quartets);
 
 /* Several plans (each with its own D and K, all on one device) in fused
  * launches: one screening pass and one ERI launch per class cover every
@@ -221,6 +276,24 @@ hfx_status hfx_autotune(hfx_plan_t plan, const double *d_dev, double *k_dev, int
 hfx_status hfx_export(hfx_plan_t plan, int32_t what, void *host, int64_t *n);
 
 hfx_status hfx_plan_destroy(hfx_plan_t plan);
+
+/* NAO2GTO (Introduction and Background: numerical atomic orbitals with a
+ * strict cutoff, each fitted by several GTOs so that the ERIs are
+ * analytical): fit the radial function radial[i] = R(r[i]) of angular
+ * momentum l on the grid r (n_r increasing points >= 0, host memory) by
+ * f(r) = sum_k c_k r^l exp(-a_k r^2), k < n_gto, minimising
+ * sum_i w_i (R(r_i) - f(r_i))^2 with w_i = r_i^2 dr_i (trapezoid weights of
+ * the radial measure).  Coefficients by weighted linear least squares for
+ * given exponents, log-exponents by Levenberg-Marquardt from an
+ * even-tempered start spanning the grid.  exps_out, coefs_out: n_gto host
+ * doubles, exponents ascending; coefficients raw (multiplying r^l e^{-a r^2};
+ * hfx_plan normalises a contraction, so they enter hfx_system.prim_coef as
+ * they are).  *rms_out (nullable): sqrt(objective / sum_i w_i R_i^2).
+ * HFX_ERR_INVALID for l outside 0..HFX_MAX_L, n_gto outside
+ * 1..HFX_MAX_PRIM, fewer than 2 n_gto + 2 points, a non-increasing grid or a
+ * zero function.  Host only: needs no device. */
+hfx_status hfx_nao2gto_fit(int32_t l, int32_t n_r, const double *r, const double *radial, int32_t n_gto,
+                           double *exps_out, double *coefs_out, double *rms_out);
 
 const char *hfx_last_error(void);
 

@@ -65,6 +65,11 @@ def lib():
         L.oracle_block_offsets.argtypes = [ctypes.c_void_p, i64p]
         L.oracle_schwarz.argtypes = [ctypes.c_void_p, dp]
         L.oracle_set_density.argtypes = [ctypes.c_void_p, dp, dp]
+        L.oracle_set_pmax.argtypes = [ctypes.c_void_p, dp]
+        L.oracle_set_q.argtypes = [ctypes.c_void_p, dp]
+        L.oracle_quartets_bra.restype = ctypes.c_int64
+        L.oracle_quartets_bra.argtypes = [ctypes.c_void_p, ctypes.c_int, ctypes.c_int64, i64p, ctypes.c_int64,
+                                          i32p, dp]
         L.oracle_density_cart.restype = ctypes.c_int64
         L.oracle_density_cart.argtypes = [ctypes.c_void_p, i64p, dp]
         L.oracle_build_K.restype = ctypes.c_int64
@@ -132,6 +137,72 @@ def sph_matrix(l: int, spherical: bool = True) -> np.ndarray:
     return T[: n.value * nc].reshape(n.value, nc).copy()
 
 
+def nao2gto_fit(l, r, radial, n_gto):
+    """GTO fit of a numerical radial function (NAO2GTO: the paper fits each
+    numerical orbital with several GTOs; it gives no procedure, so this is
+    the reading): minimise sum_i w_i (R_i - sum_k c_k r_i^l exp(-a_k r_i^2))^2,
+    w_i = r_i^2 dr_i (trapezoid), with even-tempered exponents a_k = a_0 b^k,
+    coefficients by weighted linear least squares (numpy lstsq) for given
+    (a_0, b); (log a_0, log b) by brute force over a 64 x 48 grid of the box
+    a_0 in [0.1 / r_max^2, 5], b in [1.5, 8], refined by scipy's bounded
+    Nelder-Mead.  Returns (exponents ascending, coefficients, relative rms)."""
+    from scipy.optimize import minimize
+    r = np.asarray(r, dtype=float)
+    R = np.asarray(radial, dtype=float)
+    dr = np.zeros_like(r)
+    dr[1:] += 0.5 * np.diff(r)
+    dr[:-1] += 0.5 * np.diff(r)
+    sw = np.sqrt(r * r * dr)
+    lo = np.array([np.log(0.1 / r[-1] ** 2), np.log(1.5)])
+    hi = np.array([np.log(5.0), np.log(8.0) if n_gto > 1 else np.log(1.5)])
+
+    def fit(p):
+        p = np.clip(p, lo, hi)
+        a = np.exp(p[0] + np.arange(n_gto) * p[1])
+        A = (r ** l)[:, None] * np.exp(-a[None, :] * (r * r)[:, None])
+        c, *_ = np.linalg.lstsq(sw[:, None] * A, sw * R, rcond=None)
+        return a, c, float(np.sum((sw * (R - A @ c)) ** 2))
+
+    ga = np.linspace(lo[0], hi[0], 64)
+    gb = np.linspace(lo[1], hi[1], 48) if n_gto > 1 else np.array([lo[1]])
+    vals = np.array([[fit(np.array([x, y]))[2] for y in gb] for x in ga])
+    i, j = np.unravel_index(np.argmin(vals), vals.shape)
+    p0 = np.array([ga[i], gb[j]])
+    if n_gto > 1:
+        sol = minimize(lambda p: fit(p)[2], p0, method="Nelder-Mead", bounds=list(zip(lo, hi)),
+                       options={"xatol": 1e-12, "fatol": 0.0, "maxiter": 20000, "maxfev": 40000})
+        p0 = sol.x
+    else:
+        sol = minimize(lambda x: fit(np.array([x[0], lo[1]]))[2], p0[:1], method="Nelder-Mead",
+                       bounds=[(lo[0], hi[0])], options={"xatol": 1e-12, "fatol": 0.0, "maxiter": 20000})
+        p0 = np.array([sol.x[0], lo[1]])
+    a, c, f = fit(p0)
+    return a, c, float(np.sqrt(f / np.sum((sw * R) ** 2)))
+
+
+def kspace(system, blocks, offsets, K, kpts, alpha):
+    """Exchange part of the Hamiltonian at k-points from real-space K blocks
+    (Background section: Bloch sum of the Hamiltonian applied to Eq. H-HFX
+    with its -1/2, times the exact-exchange fraction alpha):
+    H(k)_{mu nu} = -(alpha/2) sum_G K^G_{mu nu} exp(i k.(T_G + r_nu - r_mu)).
+    Plain loop over the pattern blocks; returns complex (nk, nbf, nbf)."""
+    from systems import nfunc
+    ls = np.asarray(system.shell_l)
+    nf = np.array([nfunc(int(l), system.spherical_d) for l in ls])
+    fo = np.concatenate([[0], np.cumsum(nf)])
+    nbf = int(fo[-1])
+    r = np.asarray(system.atom_xyz, dtype=float)[np.asarray(system.shell_atom)]
+    lat = np.zeros((3, 3)) if system.lattice is None else np.asarray(system.lattice, dtype=float)
+    kp = np.asarray(kpts, dtype=float).reshape(-1, 3)
+    H = np.zeros((len(kp), nbf, nbf), dtype=complex)
+    for b, (I, J, n1, n2, n3) in enumerate(np.asarray(blocks)):
+        d = n1 * lat[0] + n2 * lat[1] + n3 * lat[2] + r[J] - r[I]
+        v = np.asarray(K[offsets[b]:offsets[b + 1]]).reshape(nf[I], nf[J])
+        for k in range(len(kp)):
+            H[k, fo[I]:fo[I + 1], fo[J]:fo[J + 1]] += -0.5 * alpha * v * np.exp(1j * float(kp[k] @ d))
+    return H
+
+
 # ---------------------------------------------------------------- system
 class Oracle:
     """Oracle state for one system: its own pattern, Q, P_max and K."""
@@ -187,6 +258,49 @@ class Oracle:
         self.Pmax = np.zeros(len(self.blocks))
         lib().oracle_set_density(self.h, _p(d), _p(self.Pmax))
         return self.Pmax
+
+    def set_q(self, q: np.ndarray) -> None:
+        """Replace the Schwarz factors (one per block) used by the screening."""
+        q = np.ascontiguousarray(q, dtype=np.float64)
+        assert q.shape == (len(self.blocks),)
+        self.Q = q.copy()
+        lib().oracle_set_q(self.h, _p(q))
+
+    def quartets_of_bra_blocks(self, bra_blocks, gR: int = 3):
+        """Kept ordered quartets whose bra block is one of ``bra_blocks``
+        (every ket block, G in the cube |G_i| <= gR): (rows[n,13], bounds[n])."""
+        if self.Q is None:
+            self.schwarz()
+        bb = np.ascontiguousarray(bra_blocks, dtype=np.int64)
+        n = lib().oracle_quartets_bra(self.h, gR, len(bb), _p(bb, ctypes.c_int64), 0, None, None)
+        rows = np.zeros((max(n, 1), 13), dtype=np.int32)
+        bnd = np.zeros(max(n, 1))
+        lib().oracle_quartets_bra(self.h, gR, len(bb), _p(bb, ctypes.c_int64), n, _p(rows, ctypes.c_int32), _p(bnd))
+        return rows[:n], bnd[:n]
+
+    def set_pmax(self, pmax: np.ndarray) -> None:
+        """Replace the block maxima used by the screening predicate."""
+        p = np.ascontiguousarray(pmax, dtype=np.float64)
+        assert p.shape == (len(self.blocks),)
+        self.Pmax = p.copy()
+        lib().oracle_set_pmax(self.h, _p(p))
+
+    def build_K_spin(self, d_alpha: np.ndarray, d_beta: np.ndarray):
+        """Collinear spin: K of each spin density (Eq. H-HFX per spin), both
+        screened with one predicate whose block maxima are the larger of the
+        two spins' (so that one quartet list serves both).  Returns
+        (K_alpha, K_beta)."""
+        if self.Q is None:
+            self.schwarz()
+        pb = self.set_density(d_beta)
+        pa = self.set_density(d_alpha)
+        pm = np.maximum(pa, pb)
+        self.set_pmax(pm)
+        ka, _ = self.build_K()
+        self.set_density(d_beta)
+        self.set_pmax(pm)
+        kb, _ = self.build_K()
+        return ka, kb
 
     def density_cart(self):
         """Cartesian density blocks of the last set_density: (block offsets

@@ -576,6 +576,13 @@ int64_t oracle_density_cart(void *h, int64_t *coff_out, double *dc_out) {
   return s->nnz_c;
 }
 
+/* Replace the block maxima the screening uses (e.g. by the larger of two
+ * spin densities' maxima, so that one predicate serves both spins). */
+void oracle_set_pmax(void *h, const double *pmax) {
+  osys *s = (osys *)h;
+  memcpy(s->Pmax, pmax, sizeof(double) * s->nblk);
+}
+
 static double pm(const osys *s, int I, int J, int n1, int n2, int n3) {
   int64_t b = find_block(s, I, J, n1, n2, n3);
   return b < 0 ? 0.0 : s->Pmax[b];
@@ -718,10 +725,18 @@ int64_t oracle_K_from_quartets(void *h, int64_t n, const int32_t *rows, double *
  * (I, J, N1, N2, N3, K, L, M1, M2, M3, G1, G2, G3) with H = G + M; out_b[r]
  * is the bound (Q_IJ * Q_KL) * P_scr.  Writes at most cap rows and returns
  * the total count. */
-int64_t oracle_quartets(void *h, int gR, int64_t cap, int32_t *out_i, double *out_b) {
+/* Kept ordered quartets (I^0 J^N | K^G L^(G+M)) of the predicate of
+ * Eq. schwarz and Eq. dmscreening, bra block pb over the nbra blocks in
+ * bra_blocks (NULL: every block), ket block qb over every block, G in the
+ * cube |G_i| <= gR (molecules: G = 0).  Rows of 13 ints (I, J, N, K, L, M,
+ * G) and bounds, at most cap of them written; returns the count. */
+int64_t oracle_quartets_bra(void *h, int gR, int64_t nbra, const int64_t *bra_blocks, int64_t cap,
+                            int32_t *out_i, double *out_b) {
   osys *s = (osys *)h;
   int64_t cnt = 0;
-  for (int64_t pb = 0; pb < s->nblk; ++pb) {
+  const int64_t nb = bra_blocks ? nbra : s->nblk;
+  for (int64_t ib = 0; ib < nb; ++ib) {
+    const int64_t pb = bra_blocks ? bra_blocks[ib] : ib;
     const int32_t *y = s->blk + 5 * pb;
     int I = y[0], J = y[1], N[3] = {y[2], y[3], y[4]};
     for (int64_t qb = 0; qb < s->nblk; ++qb) {
@@ -754,6 +769,17 @@ int64_t oracle_quartets(void *h, int gR, int64_t cap, int32_t *out_i, double *ou
     }
   }
   return cnt;
+}
+
+int64_t oracle_quartets(void *h, int gR, int64_t cap, int32_t *out_i, double *out_b) {
+  return oracle_quartets_bra(h, gR, 0, NULL, cap, out_i, out_b);
+}
+
+/* Replace the Schwarz factors (one per block) the screening uses, e.g. by
+ * another implementation's, to compare the quartet selection alone. */
+void oracle_set_q(void *h, const double *q) {
+  osys *s = (osys *)h;
+  memcpy(s->Q, q, sizeof(double) * s->nblk);
 }
 
 /* Evaluate the given ordered quartets (rows of 13 ints as in

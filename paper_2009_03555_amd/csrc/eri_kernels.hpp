@@ -23,11 +23,15 @@ constexpr int prim_unroll(int cb, int ck) {
 // BD = (B,D,G+nD-nB); absent blocks (-1) drop their terms.
 //   K[AC][a][c] += w sum_bd v D[BD][b][d]      K[BC][b][c] += w sum_ad v D[AD][a][d]
 //   K[AD][a][d] += w sum_bc v D[BC][b][c]      K[BD][b][d] += w sum_ac v D[AC][a][c]
+// A collinear-spin build digests the same integrals once per spin density.
 template <class C>
 __device__ __forceinline__ void digest(const DevSys &s, int bAC, int bAD, int bBC, int bBD, const double *v,
-                                       double w, const double *__restrict__ Dc, double *__restrict__ K4) {
+                                       double w, const double *__restrict__ Dc0, double *__restrict__ K40) {
   constexpr int NA = C::NA, NB = C::NB, NC = C::NC, ND = C::ND;
   auto V = [&](int a, int b, int c, int d) { return v[((a * NB + b) * NC + c) * ND + d]; };
+  for (int sp = 0; sp < s.nspin; ++sp) {
+  const double *__restrict__ Dc = Dc0 + sp * s.spin_stride;
+  double *__restrict__ K4 = K40 + sp * s.spin_stride;
   if (bAC >= 0 && bBD >= 0) {
     const double *D = Dc + s.blk_coff[bBD];
     double dv[NB * ND];
@@ -99,6 +103,7 @@ __device__ __forceinline__ void digest(const DevSys &s, int bAC, int bAD, int bB
           for (int c = 0; c < NC; ++c) acc = fma(V(a, b, c, d), dv[a * NC + c], acc);
         unsafeAtomicAdd(K + b * ND + d, w * acc);
       }
+  }
   }
 }
 

@@ -156,13 +156,15 @@ __device__ __forceinline__ void digest_w(const double *v, const DevSys &s, int4 
                                          int g2, int g3, const QuartetBlocks &qb, int lane) {
   constexpr int NA = ncart(class_la(CB)), NB = ncart(class_lb(CB)), NC = ncart(class_la(CK)),
                 ND = ncart(class_lb(CK));
-  const double *__restrict__ Dc = s.Dc;
-  double *__restrict__ K4 = s.K4;
   const int bAC = qb.AC, bAD = qb.AD, bBC = qb.BC, bBD = qb.BD;
   double w = 1.0;
   if (bi.w & 1) w *= 0.5;
   if (ki.w & 1) w *= 0.5;
   if (bra == ket && g1 == 0 && g2 == 0 && g3 == 0) w *= 0.5;
+  // a collinear-spin build digests the same integrals once per spin density
+  for (int sp = 0; sp < s.nspin; ++sp) {
+  const double *__restrict__ Dc = s.Dc + sp * s.spin_stride;
+  double *__restrict__ K4 = s.K4 + sp * s.spin_stride;
   if (bAC >= 0 && bBD >= 0 && lane < NA * NC) {
     const double *D = Dc + s.blk_coff[bBD];
     const int a = lane / NC, c = lane - a * NC;
@@ -202,6 +204,7 @@ __device__ __forceinline__ void digest_w(const double *v, const DevSys &s, int4 
 #pragma unroll
       for (int c = 0; c < NC; ++c) sum = fma(v[((a * NB + b) * NC + c) * ND + d], D[a * NC + c], sum);
     unsafeAtomicAdd(K4 + s.blk_coff[bBD] + lane, w * sum);
+  }
   }
 }
 

@@ -35,6 +35,9 @@ hfx_status fail(hfx_status st, const std::string &msg) {
 
 constexpr uint32_t kMagic = 0x48465850u;  // "HFXP"
 constexpr double kPrimDrop = 1e-20;      // primitive-pair bound below which the ERI path skips it
+// quartets a list holds at once unless hfx_set_list_limit says otherwise
+// (16 GiB of list); longer lists are evaluated in chunks
+constexpr int64_t kDefaultMaxList = (int64_t)1 << 31;
 
 bool lexpos(int a, int b, int c) { return a > 0 || (a == 0 && (b > 0 || (b == 0 && c >= 0))); }
 
@@ -90,6 +93,15 @@ struct DevMem {
     total = 0;
   }
 };
+
+// device bytes of a one-plan batch's work arrays for nitems screening work
+// items (counts, offsets, scan block sums, segment bounds, flags, counters;
+// each array 256-byte aligned), lists excluded
+size_t work_bytes(int64_t nitems) {
+  auto a = [](size_t b) { return (b + 255) & ~(size_t)255; };
+  return a(4 * (size_t)(nitems + 1)) + a(8 * (size_t)(nitems + 1)) + a(8 * (size_t)((nitems + 1023) / 1024 + 2)) +
+         2 * a(8 * (size_t)kNQuartetClass * 2) + a(8) + a(8 * (size_t)kNQuartetClass);
+}
 
 }  // namespace
 
@@ -159,7 +171,30 @@ struct hfx_plan_s {
   CoopDev coop[kNQuartetClass] = {};
   // ---- cached one-plan batch (hfx_build_K)
   struct Batch *self_batch = nullptr;
+  int64_t max_list = kDefaultMaxList;  // quartets a build's list holds at once
+  int device = -1;                     // device current at hfx_plan
+  // collinear-spin builds: both spins' D_cart and K4 (allocated on the
+  // first such build) and their one-plan batch
+  double *d_Dc_spin = nullptr, *d_K4_spin = nullptr;
+  struct Batch *spin_batch = nullptr;
+  // k-space assembly (made on its first call): shell pairs of the pattern
+  // with their block ranges, packed block images, shell function offsets,
+  // and room for the k-points
+  int4 *d_kpairs = nullptr;
+  int n_kpairs = 0;
+  int32_t *d_blk_img = nullptr, *d_func_off = nullptr;
+  int64_t nbf = 0;
+  double *d_kpts = nullptr;
+  int kpts_cap = 0;
 };
+
+// the plan's own one-plan batch
+hfx_status plan_attach(hfx_plan_s *P);
+
+namespace hfx {
+// status with a message for hfx_last_error, for the other host units
+hfx_status report_error(hfx_status st, const char *msg) { return fail(st, msg); }
+}  // namespace hfx
 
 namespace {
 
@@ -278,6 +313,14 @@ hfx_status build_host(hfx_plan_s &P, const hfx_system *s) {
       }
       box[i] = (int)std::ceil(P.cutoff * P.recn[i] + (fmax - fmin)) + 1;
       if (box[i] > 100) return fail(HFX_ERR_UNSUPPORTED, "pair cutoff spans too many lattice images");
+      // ket translations of kept quartets: a pair's midpoint lies within
+      // cutoff/2 of its home-cell atom and the screening box adds both pair
+      // half-lengths and the cutoff, so |G_i| <= span of the atoms'
+      // fractional coordinates + 3 cutoff |b_i|; the quartet encoding holds
+      // -16..15
+      const int gmax = (int)std::ceil((fmax - fmin) + 3.0 * P.cutoff * P.recn[i]) + 1;
+      if (gmax > 15)
+        return fail(HFX_ERR_UNSUPPORTED, "pair cutoff too long for the cell: ket translations could exceed 15 cells");
     }
   }
 
@@ -662,6 +705,8 @@ hfx_status upload_plan(hfx_plan_s &P) {
   s.boys = P.d_boys;
   s.Dc = P.d_Dc;
   s.K4 = P.d_K4;
+  s.nspin = 1;
+  s.spin_stride = P.nnz_c;
   for (int c = 0; c <= kNPairClass; ++c) s.class_start[c] = P.class_start[c];
   HIPCHK(P.mem.alloc(&P.d_sys1, 1));
   HIPCHK(hipMemcpyAsync(P.d_sys1, &P.ds, sizeof(DevSys), hipMemcpyHostToDevice, P.stream));
@@ -695,7 +740,7 @@ hfx_status run_schwarz(hfx_plan_s &P) {
 // Algorithmic floating-point operations of the implemented recursions
 // (FMA = 2, add/mul/div/sqrt = 1), per primitive quartet and per contracted
 // quartet of a class; mirrors os_hgp.hpp term by term.
-void class_flops(int la, int lb, int lc, int ld, int op, double &per_prim, double &per_quartet) {
+void class_flops(int la, int lb, int lc, int ld, int op, int nspin, double &per_prim, double &per_quartet) {
   const int EB = la + lb, FK = lc + ld, L = EB + FK;
   auto cart = [](int l, int c, int &x, int &y, int &z) {
     int a = 0;
@@ -743,8 +788,10 @@ void class_flops(int la, int lb, int lc, int ld, int op, double &per_prim, doubl
   for (int b = 1; b <= lb; ++b) g += 2.0 * ncart(b) * (noff(EB - b + 1) - noff(la)) * NF;
   for (int d = 1; d <= ld; ++d) g += 2.0 * ncart(d) * (noff(FK - d + 1) - noff(lc)) * ncart(la) * ncart(lb);
   const int NOUT = ncart(la) * ncart(lb) * ncart(lc) * ncart(ld);
-  g += 8.0 * NOUT;  // four digest contractions, one FMA per integral each
-  g += 2.0 * (ncart(la) * ncart(lc) + ncart(lb) * ncart(lc) + ncart(la) * ncart(ld) + ncart(lb) * ncart(ld));
+  // four digest contractions per spin density, one FMA per integral each,
+  // and the weighting of their results
+  g += nspin * (8.0 * NOUT +
+                2.0 * (ncart(la) * ncart(lc) + ncart(lb) * ncart(lc) + ncart(la) * ncart(ld) + ncart(lb) * ncart(ld)));
   per_quartet = g;
 }
 
@@ -769,10 +816,12 @@ hfx_status hfx_footprint(const hfx_system *sys, size_t *device_bytes, size_t *li
   b += P.blocks.size() * (sizeof(int2) + 8 + 8 + 4 + 1 + 8) + 16;
   b += (size_t)P.nnz_c * 16;
   b += (size_t)kBoysRows * kBoysCols * 8;
-  // screening work: one item per (class region, bra pair)
+  // screening work: one item per (class region, bra pair), with its counts,
+  // offsets and the rest of a batch's work arrays, for the plan's own batch
+  // and for its share of a fused multi-plan batch
   int64_t nitems = 0;
   for (int cb = 0; cb < kNPairClass; ++cb) nitems += (int64_t)(cb + 1) * (P.class_start[cb + 1] - P.class_start[cb]);
-  b += (size_t)nitems * (sizeof(int4) + 4 + 8) + 8 + sizeof(DevSys);
+  b += 2 * ((size_t)nitems * sizeof(int4) + sizeof(DevSys) + (size_t)kNQuartetClass * 2 * 8 + work_bytes(nitems));
   *device_bytes = b;
   if (list_bytes_per_quartet) *list_bytes_per_quartet = sizeof(uint64_t);
   return HFX_OK;
@@ -787,6 +836,7 @@ hfx_status hfx_plan(const hfx_system *sys, void *stream, hfx_plan_t *out) {
   P->stream = (hipStream_t)stream;
   st = build_host(*P, sys);
   if (st == HFX_OK) st = upload_plan(*P);
+  if (st == HFX_OK) st = plan_attach(P);
   if (st != HFX_OK) {
     P->mem.release();
     P->magic = 0;
@@ -828,10 +878,27 @@ hfx_status hfx_schwarz(hfx_plan_t plan, double *q_host, int64_t *n_pairs) {
 
 // ===================================================================
 // Batches: one or more plans built by fused launches.  A batch owns the
-// screening work items of its plans (region, bra pair, plan), the class-
-// segment bounds on the device, the quartet lists and an optional HIP graph
-// of the whole build.
+// screening work items of its plans (region, bra pair, plan), the per-build
+// work arrays (counts, offsets, class-segment bounds, quartet lists, error
+// flags) and an optional HIP graph of the whole build.
 // ===================================================================
+
+// Per-build device work arrays.  A batch allocates its own (lists grow to
+// the screened size up to the batch's list limit).  Work arrays of fixed
+// capacity (fixed = true: memory the build may not reallocate) evaluate
+// every list in chunks, and list32 may alias list.
+struct Work {
+  int32_t *counts = nullptr;
+  int64_t *offsets = nullptr;
+  int64_t *tiles = nullptr;  // block sums of the scan
+  int64_t *seg64 = nullptr, *seg32 = nullptr;
+  int32_t *err = nullptr;
+  unsigned long long *nprim = nullptr;
+  uint64_t *list = nullptr, *list32 = nullptr;
+  int64_t cap = 0, cap32 = 0;
+  bool fixed = false;
+};
+
 struct Batch {
   std::vector<hfx_plan_s *> plans;
   int op = 0;
@@ -841,19 +908,15 @@ struct Batch {
   DevSys *d_sys = nullptr;
   int4 *d_items = nullptr;
   int64_t nitems = 0;
-  int32_t *d_counts = nullptr;
-  int64_t *d_offsets = nullptr;
-  int64_t *d_scan_tmp = nullptr;  // block sums
   std::vector<int64_t> seg_items;  // [kNQuartetClass][n + 1]
   int64_t *d_seg_items = nullptr;
-  int64_t *d_seg64 = nullptr, *d_seg32 = nullptr;
-  std::vector<int64_t> h_seg64, h_seg32;
-  uint64_t *d_list = nullptr, *d_list32 = nullptr;
-  int64_t cap = 0, cap32 = 0;
+  Work w;                          // the batch's own work arrays (lists allocated on demand)
+  int64_t max_list = 0;            // quartets a list may hold at once (larger lists run in chunks)
+  int nspin = 1;                   // densities per plan (2: collinear spin, one ERI evaluation)
+  std::vector<int64_t> h_seg64, h_seg32;  // whole-list class-segment bounds of the last eager build
   int64_t nq64 = 0, nq32 = 0;
-  int32_t *d_err = nullptr;
-  unsigned long long *d_nprim = nullptr;
-  bool have_counts = false;  // an eager build has filled h_seg* / nq*
+  int64_t n_chunks = 0;            // list chunks of the last eager build (0: lists whole)
+  bool have_counts = false;        // an eager build has filled h_seg* / nq*
   // graph of the build for fixed (D, K) pointers
   hipGraph_t graph = nullptr;
   hipGraphExec_t gexec = nullptr;
@@ -868,9 +931,10 @@ struct Batch {
     graph = nullptr;
     if (cap_stream) (void)hipStreamDestroy(cap_stream);
     cap_stream = nullptr;
-    if (d_list) (void)hipFree(d_list);
-    if (d_list32) (void)hipFree(d_list32);
-    d_list = d_list32 = nullptr;
+    if (w.list) (void)hipFree(w.list);
+    if (w.list32) (void)hipFree(w.list32);
+    w.list = w.list32 = nullptr;
+    w.cap = w.cap32 = 0;
     mem.release();
   }
   int n() const { return (int)plans.size(); }
@@ -892,15 +956,62 @@ void launch_variant(int v, int cb, int ck, int op, const CoopDev &cd, const SegL
   }
 }
 
-hfx_status batch_init(Batch &B, const std::vector<hfx_plan_s *> &plans) {
+// bytes of the per-build work arrays other than the lists, for nitems
+// screening work items and n plans
+struct WorkLayout {
+  size_t counts, offsets, tiles, seg, err, nprim, total;
+};
+size_t align256(size_t b) { return (b + 255) & ~(size_t)255; }
+WorkLayout work_layout(int64_t nitems, int n) {
+  WorkLayout L;
+  L.counts = align256(sizeof(int32_t) * (size_t)(nitems + 1));
+  L.offsets = align256(sizeof(int64_t) * (size_t)(nitems + 1));
+  L.tiles = align256(sizeof(int64_t) * (size_t)((nitems + 1023) / 1024 + 2));
+  L.seg = align256(sizeof(int64_t) * (size_t)kNQuartetClass * (n + 1));
+  L.err = align256(2 * sizeof(int32_t));
+  L.nprim = align256(kNQuartetClass * sizeof(unsigned long long));
+  L.total = L.counts + L.offsets + L.tiles + 2 * L.seg + L.err + L.nprim;
+  return L;
+}
+// point w's arrays (not the lists) into base, laid out as work_layout says
+void work_place(Work &w, char *base, const WorkLayout &L) {
+  char *p = base;
+  w.counts = (int32_t *)p;
+  p += L.counts;
+  w.offsets = (int64_t *)p;
+  p += L.offsets;
+  w.tiles = (int64_t *)p;
+  p += L.tiles;
+  w.seg64 = (int64_t *)p;
+  p += L.seg;
+  w.seg32 = (int64_t *)p;
+  p += L.seg;
+  w.err = (int32_t *)p;
+  p += L.err;
+  w.nprim = (unsigned long long *)p;
+}
+
+hfx_status batch_init(Batch &B, const std::vector<hfx_plan_s *> &plans, int nspin = 1) {
   B.plans = plans;
+  B.nspin = nspin;
   B.op = plans[0]->op;
   B.stream = plans[0]->stream;
   B.mixed = false;
-  for (auto *P : plans) B.mixed |= P->precision == HFX_MIXED;
+  B.max_list = INT64_MAX;
+  for (auto *P : plans) {
+    B.mixed |= P->precision == HFX_MIXED;
+    B.max_list = std::min(B.max_list, P->max_list);
+  }
   const int n = (int)plans.size();
   std::vector<DevSys> sys(n);
-  for (int i = 0; i < n; ++i) sys[i] = plans[i]->ds;
+  for (int i = 0; i < n; ++i) {
+    sys[i] = plans[i]->ds;
+    if (nspin == 2) {
+      sys[i].Dc = plans[i]->d_Dc_spin;
+      sys[i].K4 = plans[i]->d_K4_spin;
+      sys[i].nspin = 2;
+    }
+  }
   // items ordered by (region, plan, bra pair): every class segment of the
   // fused list is contiguous and holds plan 0's quartets, then plan 1's, ...
   std::vector<int4> items;
@@ -922,27 +1033,27 @@ hfx_status batch_init(Batch &B, const std::vector<hfx_plan_s *> &plans) {
   HIPCHK(B.mem.alloc(&B.d_items, items.size()));
   if (!items.empty())
     HIPCHK(hipMemcpyAsync(B.d_items, items.data(), items.size() * sizeof(int4), hipMemcpyHostToDevice, B.stream));
-  HIPCHK(B.mem.alloc(&B.d_counts, items.size()));
-  HIPCHK(B.mem.alloc(&B.d_offsets, items.size() + 1));
-  HIPCHK(B.mem.alloc(&B.d_scan_tmp, (items.size() + 1023) / 1024 + 2));
   HIPCHK(B.mem.alloc(&B.d_seg_items, B.seg_items.size()));
   HIPCHK(hipMemcpyAsync(B.d_seg_items, B.seg_items.data(), B.seg_items.size() * 8, hipMemcpyHostToDevice, B.stream));
-  HIPCHK(B.mem.alloc(&B.d_seg64, B.seg_items.size()));
-  HIPCHK(B.mem.alloc(&B.d_seg32, B.seg_items.size()));
-  HIPCHK(B.mem.alloc(&B.d_err, 2));
-  HIPCHK(B.mem.alloc(&B.d_nprim, kNQuartetClass));
+  const WorkLayout L = work_layout(B.nitems, n);
+  char *wbase = nullptr;
+  HIPCHK(B.mem.alloc(&wbase, L.total));
+  work_place(B.w, wbase, L);
   B.h_seg64.assign(B.seg_items.size(), 0);
   B.h_seg32.assign(B.seg_items.size(), 0);
   HIPCHK(hipStreamSynchronize(B.stream));
   return HFX_OK;
 }
 
-hfx_status ensure_cap(uint64_t **list, int64_t *cap, int64_t need) {
+// grow a list to hold `need` entries (with headroom, at most `limit`)
+hfx_status ensure_cap(uint64_t **list, int64_t *cap, int64_t need, int64_t limit) {
   if (need <= *cap && *list) return HFX_OK;
   if (*list) HIPCHK(hipFree(*list));
   *list = nullptr;
   *cap = 0;
-  const int64_t c = need + need / 4 + 4096;
+  int64_t c = need + need / 4 + 4096;
+  if (c > limit) c = limit;
+  if (c < need) c = need;
   hipError_t e = hipMalloc((void **)list, (size_t)c * sizeof(uint64_t));
   if (e != hipSuccess) return fail(HFX_ERR_OOM, "quartet list allocation failed");
   *cap = c;
@@ -958,93 +1069,183 @@ void drop_graph(Batch &B) {
   B.g_k.clear();
 }
 
-// One screening pass (count, scan, bounds; eager: host read + allocation;
-// fill).  graph: no host interaction, the list must already have capacity.
-hfx_status screen_pass(Batch &B, int mode, bool graph, uint64_t **list, int64_t *cap, int64_t *d_seg,
-                       std::vector<int64_t> &h_seg, int64_t *total) {
-  launch_screen(B.d_sys, B.d_items, B.nitems, B.d_counts, B.d_offsets, nullptr, 0, B.d_err, false, mode, B.stream);
-  HIPCHK(scan_counts(B.d_counts, B.d_offsets, B.nitems, B.d_scan_tmp, B.stream));
-  launch_gather_bounds(B.d_offsets, B.d_seg_items, d_seg, (int)B.seg_items.size(), graph ? *cap : INT64_MAX,
-                       B.stream);
-  if (!graph) {
-    HIPCHK(hipMemcpyAsync(h_seg.data(), d_seg, h_seg.size() * 8, hipMemcpyDeviceToHost, B.stream));
-    HIPCHK(hipStreamSynchronize(B.stream));
-    *total = h_seg.empty() ? 0 : h_seg.back();
-    const uint64_t *before = *list;
-    hfx_status st = ensure_cap(list, cap, *total);
-    if (st != HFX_OK) return st;
-    if (*list != before) drop_graph(B);  // a captured graph holds the old list
+// ERI launches of every class over one list whose class-segment bounds are
+// on the device at d_seg; h_seg: the same bounds on the host (grid sizes),
+// or nullptr (graph: grids that drain any count).  f32: the FP32 list.
+void launch_classes(Batch &B, Work &W, bool f32, const uint64_t *list, int64_t *d_seg, const int64_t *h_seg) {
+  const int n = B.n();
+  hfx_plan_s &P0 = *B.plans[0];
+  for (int cb = kNPairClass - 1; cb >= 0; --cb)
+    for (int ck = cb; ck >= 0; --ck) {
+      const int r = region_of(cb, ck);
+      const size_t so = (size_t)r * (n + 1);
+      SegLaunch L{B.d_sys, n, d_seg + so, list, W.nprim + r, -1, B.stream, f32 ? P0.grid32[r] : P0.grid[r]};
+      if (h_seg) L.nq_hint = h_seg[so + n] - h_seg[so];
+      launch_variant(f32 ? P0.kern32[r] : P0.kern[r], cb, ck, B.op, P0.coop[r], L);
+    }
+}
+
+// A list that does not fit its buffer, in chunks of consecutive screening
+// work items (ranges of bra pairs of a class region) whose quartets fit:
+// each chunk is filled, then evaluated by the ERI kernels of every class
+// before the next chunk overwrites the buffer (stream order).  The offsets
+// of the count pass are read back to place the chunk boundaries.
+hfx_status run_chunks(Batch &B, Work &W, int mode, bool f32, uint64_t *list, int64_t cap, int64_t *d_seg) {
+  const int n = B.n();
+  const int64_t nit = B.nitems;
+  std::vector<int64_t> off((size_t)nit + 1);
+  HIPCHK(hipMemcpyAsync(off.data(), W.offsets, off.size() * sizeof(int64_t), hipMemcpyDeviceToHost, B.stream));
+  HIPCHK(hipStreamSynchronize(B.stream));
+  std::vector<int64_t> hs(B.seg_items.size());
+  int64_t i0 = 0;
+  while (i0 < nit) {
+    const int64_t base = off[i0];
+    const auto it = std::upper_bound(off.begin() + i0 + 1, off.end(), base + cap);
+    const int64_t i1 = (int64_t)(it - off.begin()) - 1;
+    if (i1 <= i0)
+      return fail(HFX_ERR_OOM, "one screening work item (a bra pair against a ket class) has more quartets (" +
+                                   std::to_string(off[i0 + 1] - base) + ") than the list capacity (" +
+                                   std::to_string(cap) + ")");
+    const int64_t end = off[i1];
+    if (end > base) {
+      launch_screen(B.d_sys, B.d_items + i0, i1 - i0, W.counts, W.offsets + i0, list, base, cap, W.err, true, mode,
+                    B.stream);
+      launch_gather_bounds(W.offsets, B.d_seg_items, d_seg, (int)B.seg_items.size(), base, end, B.stream);
+      for (size_t k = 0; k < hs.size(); ++k) {
+        const int64_t v = off[B.seg_items[k]];
+        hs[k] = std::min(std::max(v, base), end) - base;
+      }
+      launch_classes(B, W, f32, list, d_seg, hs.data());
+      ++B.n_chunks;
+    }
+    i0 = i1;
   }
-  launch_screen(B.d_sys, B.d_items, B.nitems, B.d_counts, B.d_offsets, *list, *cap, B.d_err, true, mode, B.stream);
+  (void)n;
   return HFX_OK;
 }
 
 // Enqueue the whole build of a batch on its stream.  graph = true: nothing
-// here waits for the device (the sequence is being captured).
-hfx_status enqueue_build(Batch &B, const double *const *d_dev, double *const *k_dev, bool graph, hipEvent_t *ev,
-                         hipEvent_t *evc) {
+// here waits for the device (the sequence is being captured) and every list
+// is whole.  Eager: each list is counted, sized on the host and either
+// filled whole (its ERI launches follow all screening, class by class) or,
+// when it exceeds the list limit or the work arrays are fixed, evaluated
+// chunk by chunk right away.
+hfx_status enqueue_build(Batch &B, Work &W, const double *const *d_dev, double *const *k_dev, bool graph,
+                         hipEvent_t *ev, hipEvent_t *evc) {
   const int n = B.n();
-  hfx_plan_s &P0 = *B.plans[0];
   if (ev) HIPCHK(hipEventRecord(ev[0], B.stream));
+  const int ns = B.nspin;
   for (int i = 0; i < n; ++i) {
     hfx_plan_s &P = *B.plans[i];
+    double *Dc = ns == 2 ? P.d_Dc_spin : P.d_Dc;
+    double *K4 = ns == 2 ? P.d_K4_spin : P.d_K4;
     launch_zero_u64(P.d_pglob, 1, B.stream);
-    launch_density(P.ds, (int64_t)P.blocks.size(), P.d_blk_IJ, P.d_blk_off, P.d_partner, P.d_canon, P.sph, d_dev[i],
-                   P.d_Dc, B.stream);
-    launch_zero(P.d_K4, P.nnz_c, B.stream);
+    for (int sp = 0; sp < ns; ++sp)
+      launch_density(P.ds, (int64_t)P.blocks.size(), P.d_blk_IJ, P.d_blk_off, P.d_partner, P.d_canon, P.sph,
+                     d_dev[i * ns + sp], Dc + sp * P.nnz_c, sp > 0, B.stream);
+    launch_zero(K4, ns * P.nnz_c, B.stream);
   }
   if (ev) HIPCHK(hipEventRecord(ev[1], B.stream));
-  launch_zero_i32(B.d_err, 2, B.stream);
-  launch_zero_u64(B.d_nprim, kNQuartetClass, B.stream);
-  hfx_status st = screen_pass(B, B.mixed ? 1 : 0, graph, &B.d_list, &B.cap, B.d_seg64, B.h_seg64, &B.nq64);
-  if (st != HFX_OK) return st;
-  if (B.mixed) {
-    st = screen_pass(B, 2, graph, &B.d_list32, &B.cap32, B.d_seg32, B.h_seg32, &B.nq32);
-    if (st != HFX_OK) return st;
-  } else if (!graph) {
+  launch_zero_i32(W.err, 2, B.stream);
+  launch_zero_u64(W.nprim, kNQuartetClass, B.stream);
+  if (!graph) B.n_chunks = 0;
+  bool whole[2] = {false, false};
+  const int nlists = B.mixed ? 2 : 1;
+  for (int li = 0; li < nlists; ++li) {
+    const int mode = B.mixed ? 1 + li : 0;
+    const bool f32 = li == 1;
+    uint64_t **list = f32 ? &W.list32 : &W.list;
+    int64_t *cap = f32 ? &W.cap32 : &W.cap;
+    int64_t *d_seg = f32 ? W.seg32 : W.seg64;
+    std::vector<int64_t> &h_seg = f32 ? B.h_seg32 : B.h_seg64;
+    launch_screen(B.d_sys, B.d_items, B.nitems, W.counts, W.offsets, nullptr, 0, 0, W.err, false, mode, B.stream);
+    HIPCHK(scan_counts(W.counts, W.offsets, B.nitems, W.tiles, B.stream));
+    if (graph) {
+      launch_gather_bounds(W.offsets, B.d_seg_items, d_seg, (int)B.seg_items.size(), 0, *cap, B.stream);
+      launch_screen(B.d_sys, B.d_items, B.nitems, W.counts, W.offsets, *list, 0, *cap, W.err, true, mode, B.stream);
+      whole[li] = true;
+      continue;
+    }
+    launch_gather_bounds(W.offsets, B.d_seg_items, d_seg, (int)B.seg_items.size(), 0, INT64_MAX, B.stream);
+    HIPCHK(hipMemcpyAsync(h_seg.data(), d_seg, h_seg.size() * 8, hipMemcpyDeviceToHost, B.stream));
+    // the count pass has visited every kept translation: its error flag is
+    // final here, so an eager build reports it even when nobody waits
+    int32_t err[2] = {0, 0};
+    HIPCHK(hipMemcpyAsync(err, W.err, sizeof(err), hipMemcpyDeviceToHost, B.stream));
+    HIPCHK(hipStreamSynchronize(B.stream));
+    if (err[0] & 1) return fail(HFX_ERR_UNSUPPORTED, "a ket translation exceeds the quartet encoding range");
+    const int64_t total = h_seg.empty() ? 0 : h_seg.back();
+    (f32 ? B.nq32 : B.nq64) = total;
+    if (!W.fixed && total <= B.max_list) {
+      const uint64_t *before = *list;
+      hfx_status st = ensure_cap(list, cap, total, B.max_list);
+      if (st != HFX_OK) return st;
+      if (*list != before) drop_graph(B);  // a captured graph holds the old list
+      launch_screen(B.d_sys, B.d_items, B.nitems, W.counts, W.offsets, *list, 0, *cap, W.err, true, mode, B.stream);
+      whole[li] = true;
+    } else {
+      if (!W.fixed) {
+        hfx_status st = ensure_cap(list, cap, B.max_list, B.max_list);
+        if (st != HFX_OK) return st;
+        drop_graph(B);
+      }
+      hfx_status st = run_chunks(B, W, mode, f32, *list, *cap, d_seg);
+      if (st != HFX_OK) return st;
+    }
+  }
+  if (!B.mixed && !graph) {
     B.nq32 = 0;
     std::fill(B.h_seg32.begin(), B.h_seg32.end(), 0);
   }
   if (!graph) B.have_counts = true;
   if (ev) HIPCHK(hipEventRecord(ev[2], B.stream));
+  hfx_plan_s &P0 = *B.plans[0];
   for (int cb = kNPairClass - 1; cb >= 0; --cb)
     for (int ck = cb; ck >= 0; --ck) {
       const int r = region_of(cb, ck);
       const size_t so = (size_t)r * (n + 1);
       if (evc) HIPCHK(hipEventRecord(evc[r], B.stream));
-      SegLaunch L{B.d_sys, n, B.d_seg64 + so, B.d_list, B.d_nprim + r, -1, B.stream, P0.grid[r]};
-      if (!graph) L.nq_hint = B.h_seg64[so + n] - B.h_seg64[so];
-      launch_variant(P0.kern[r], cb, ck, B.op, P0.coop[r], L);
-      if (B.mixed) {
-        SegLaunch L32{B.d_sys, n, B.d_seg32 + so, B.d_list32, B.d_nprim + r, -1, B.stream, P0.grid32[r]};
-        if (!graph) L32.nq_hint = B.h_seg32[so + n] - B.h_seg32[so];
-        launch_variant(P0.kern32[r], cb, ck, B.op, P0.coop[r], L32);
+      for (int li = 0; li < nlists; ++li) {
+        if (!whole[li]) continue;
+        const bool f32 = li == 1;
+        SegLaunch L{B.d_sys, n, (f32 ? W.seg32 : W.seg64) + so, f32 ? W.list32 : W.list, W.nprim + r, -1, B.stream,
+                    f32 ? P0.grid32[r] : P0.grid[r]};
+        if (!graph) {
+          const std::vector<int64_t> &hs = f32 ? B.h_seg32 : B.h_seg64;
+          L.nq_hint = hs[so + n] - hs[so];
+        }
+        launch_variant(f32 ? P0.kern32[r] : P0.kern[r], cb, ck, B.op, P0.coop[r], L);
       }
       if (evc && r == 0) HIPCHK(hipEventRecord(evc[kNQuartetClass], B.stream));
     }
   if (ev) HIPCHK(hipEventRecord(ev[3], B.stream));
   for (int i = 0; i < n; ++i) {
     hfx_plan_s &P = *B.plans[i];
-    launch_finalize(P.ds, (int64_t)P.blocks.size(), P.d_blk_IJ, P.d_blk_off, P.d_partner, P.sph, P.d_K4, k_dev[i],
-                    B.stream);
+    const double *K4 = ns == 2 ? P.d_K4_spin : P.d_K4;
+    for (int sp = 0; sp < ns; ++sp)
+      launch_finalize(P.ds, (int64_t)P.blocks.size(), P.d_blk_IJ, P.d_blk_off, P.d_partner, P.sph, K4 + sp * P.nnz_c,
+                      k_dev[i * ns + sp], B.stream);
   }
   if (ev) HIPCHK(hipEventRecord(ev[4], B.stream));
   HIPCHK(hipGetLastError());
   return HFX_OK;
 }
 
-hfx_status check_err(Batch &B, bool *overflow) {
+hfx_status check_err(Batch &B, Work &W, bool *overflow) {
   int32_t err[2] = {0, 0};
-  HIPCHK(hipMemcpy(err, B.d_err, sizeof(err), hipMemcpyDeviceToHost));
+  HIPCHK(hipMemcpyAsync(err, W.err, sizeof(err), hipMemcpyDeviceToHost, B.stream));
+  HIPCHK(hipStreamSynchronize(B.stream));
   if (overflow) *overflow = (err[0] & 2) != 0;
   if (err[0] & 1) return fail(HFX_ERR_UNSUPPORTED, "a ket translation exceeds the quartet encoding range");
+  if ((err[0] & 2) && !overflow) return fail(HFX_ERR_DEVICE, "internal: quartet list overflow in an eager build");
   return HFX_OK;
 }
 
-void fill_info(Batch &B, hfx_build_info *info, hipEvent_t *ev, hipEvent_t *evc) {
+void fill_info(Batch &B, Work &W, hfx_build_info *info, hipEvent_t *ev, hipEvent_t *evc) {
   std::memset(info, 0, sizeof(*info));
   unsigned long long np[kNQuartetClass];
-  if (hipMemcpy(np, B.d_nprim, sizeof(np), hipMemcpyDeviceToHost) != hipSuccess) return;
+  if (hipMemcpyAsync(np, W.nprim, sizeof(np), hipMemcpyDeviceToHost, B.stream) != hipSuccess) return;
+  if (hipStreamSynchronize(B.stream) != hipSuccess) return;
   const int n = B.n();
   hfx_plan_s &P0 = *B.plans[0];
   double fl = 0.0;
@@ -1059,11 +1260,12 @@ void fill_info(Batch &B, hfx_build_info *info, hipEvent_t *ev, hipEvent_t *evc) 
       if (variant_fp32(P0.kern32[r])) info->n_fp32_quartets += q32;
       info->n_prim_quartets += (int64_t)np[r];
       double fp, fq;
-      class_flops(class_la(cb), class_lb(cb), class_la(ck), class_lb(ck), B.op, fp, fq);
+      class_flops(class_la(cb), class_lb(cb), class_la(ck), class_lb(ck), B.op, B.nspin, fp, fq);
       info->flops_class[r] = fp * (double)np[r] + fq * (double)info->n_quartets_class[r];
       fl += info->flops_class[r];
     }
   info->flops = fl;
+  info->n_chunks = B.n_chunks;
   if (ev) {
     float ms;
     if (hipEventElapsedTime(&ms, ev[0], ev[1]) == hipSuccess) info->ms_density = ms;
@@ -1086,10 +1288,11 @@ void fill_info(Batch &B, hfx_build_info *info, hipEvent_t *ev, hipEvent_t *evc) 
 
 // Run a batch build: eager, or through a captured graph (HFX_GRAPH) that is
 // re-captured when the D/K pointers change and re-run eagerly when the
-// screened list outgrows the capacity fixed at capture time.
-hfx_status run_batch(Batch &B, const double *const *d_dev, double *const *k_dev, uint32_t flags,
+// screened list outgrows the capacity fixed at capture time.  Builds whose
+// lists were chunked run eagerly.
+hfx_status run_batch(Batch &B, Work &W, const double *const *d_dev, double *const *k_dev, uint32_t flags,
                      hfx_build_info *info) {
-  const int n = B.n();
+  const int n = B.n() * B.nspin;  // D and K arrays: plan-major, spin-minor
   for (int i = 0; i < n; ++i)
     if (!d_dev[i] || !k_dev[i]) return fail(HFX_ERR_INVALID, "D or K pointer is NULL");
   for (auto *P : B.plans)
@@ -1098,15 +1301,15 @@ hfx_status run_batch(Batch &B, const double *const *d_dev, double *const *k_dev,
       if (st != HFX_OK) return st;
     }
   const bool timing = (flags & HFX_TIMING) != 0;
-  const bool use_graph = (flags & HFX_GRAPH) != 0 && !timing;
-  if (use_graph && B.have_counts) {
+  const bool use_graph = (flags & HFX_GRAPH) != 0 && !timing && !W.fixed;
+  if (use_graph && B.have_counts && B.n_chunks == 0) {
     bool same = B.gexec && (int)B.g_d.size() == n;
     for (int i = 0; same && i < n; ++i) same = B.g_d[i] == d_dev[i] && B.g_k[i] == k_dev[i];
     if (!same) {
       drop_graph(B);
       // headroom for the density-dependent list size of later SCF steps
-      hfx_status st = ensure_cap(&B.d_list, &B.cap, B.nq64);
-      if (st == HFX_OK && B.mixed) st = ensure_cap(&B.d_list32, &B.cap32, B.nq32);
+      hfx_status st = ensure_cap(&W.list, &W.cap, B.nq64, B.max_list);
+      if (st == HFX_OK && B.mixed) st = ensure_cap(&W.list32, &W.cap32, B.nq32, B.max_list);
       if (st != HFX_OK) return st;
       // capture on a private stream (the plan's stream may be the null
       // stream, which cannot be captured); the graph is launched on the
@@ -1116,7 +1319,7 @@ hfx_status run_batch(Batch &B, const double *const *d_dev, double *const *k_dev,
       HIPCHK(hipStreamBeginCapture(B.cap_stream, hipStreamCaptureModeThreadLocal));
       const hipStream_t user = B.stream;
       B.stream = B.cap_stream;
-      st = enqueue_build(B, d_dev, k_dev, true, nullptr, nullptr);
+      st = enqueue_build(B, W, d_dev, k_dev, true, nullptr, nullptr);
       hipGraph_t g = nullptr;
       hipError_t e = hipStreamEndCapture(B.cap_stream, &g);
       B.stream = user;
@@ -1133,15 +1336,15 @@ hfx_status run_batch(Batch &B, const double *const *d_dev, double *const *k_dev,
     HIPCHK(hipGraphLaunch(B.gexec, B.stream));
     HIPCHK(hipStreamSynchronize(B.stream));
     bool overflow = false;
-    hfx_status st = check_err(B, &overflow);
+    hfx_status st = check_err(B, W, &overflow);
     if (st != HFX_OK) return st;
     if (!overflow) {
       // counts of this build for the report
-      HIPCHK(hipMemcpy(B.h_seg64.data(), B.d_seg64, B.h_seg64.size() * 8, hipMemcpyDeviceToHost));
-      if (B.mixed) HIPCHK(hipMemcpy(B.h_seg32.data(), B.d_seg32, B.h_seg32.size() * 8, hipMemcpyDeviceToHost));
+      HIPCHK(hipMemcpy(B.h_seg64.data(), W.seg64, B.h_seg64.size() * 8, hipMemcpyDeviceToHost));
+      if (B.mixed) HIPCHK(hipMemcpy(B.h_seg32.data(), W.seg32, B.h_seg32.size() * 8, hipMemcpyDeviceToHost));
       B.nq64 = B.h_seg64.back();
       B.nq32 = B.mixed ? B.h_seg32.back() : 0;
-      if (info) fill_info(B, info, nullptr, nullptr);
+      if (info) fill_info(B, W, info, nullptr, nullptr);
       return HFX_OK;
     }
     // the list outgrew the captured capacity: rebuild eagerly, recapture next time
@@ -1152,11 +1355,11 @@ hfx_status run_batch(Batch &B, const double *const *d_dev, double *const *k_dev,
     for (auto &e : ev) HIPCHK(hipEventCreate(&e));
     for (auto &e : evc) HIPCHK(hipEventCreate(&e));
   }
-  hfx_status st = enqueue_build(B, d_dev, k_dev, false, timing ? ev : nullptr, timing ? evc : nullptr);
+  hfx_status st = enqueue_build(B, W, d_dev, k_dev, false, timing ? ev : nullptr, timing ? evc : nullptr);
   if (st == HFX_OK && ((flags & (HFX_SYNC | HFX_TIMING)) || info)) {
     HIPCHK(hipStreamSynchronize(B.stream));
-    st = check_err(B, nullptr);
-    if (st == HFX_OK && info) fill_info(B, info, timing ? ev : nullptr, timing ? evc : nullptr);
+    st = check_err(B, W, nullptr);
+    if (st == HFX_OK && info) fill_info(B, W, info, timing ? ev : nullptr, timing ? evc : nullptr);
   }
   if (timing) {
     for (auto &e : ev) (void)hipEventDestroy(e);
@@ -1168,6 +1371,7 @@ hfx_status run_batch(Batch &B, const double *const *d_dev, double *const *k_dev,
 // graphs of every batch that contains P (its kernel choice has changed)
 void drop_graphs_of(const hfx_plan_s *P) {
   if (P->self_batch) drop_graph(*P->self_batch);
+  if (P->spin_batch) drop_graph(*P->spin_batch);
   std::lock_guard<std::mutex> lk(g_batch_mu);
   for (Batch *B : g_batches)
     if (std::find(B->plans.begin(), B->plans.end(), P) != B->plans.end()) drop_graph(*B);
@@ -1176,14 +1380,20 @@ void drop_graphs_of(const hfx_plan_s *P) {
 // grid caps tried per kernel family (0 = default)
 const int64_t kTuneGridReg[] = {0, 256 * 16, 256 * 64};  // one-wave blocks: 262k and 1M threads
 const int64_t kTuneGridWave[] = {0, 256 * 8, 256 * 64};
+// smallest prefix the autotuner times: several times the threads of the
+// largest one-lane grid (256 * 256 one-wave blocks), so that a prefix does
+// not under-fill a grid that the whole segment fills
+constexpr int64_t kTuneMinPrefix = 4ll * 256 * 256 * 64;
 
 hfx_status tune_class(Batch &B, int cb, int ck, bool f32, int64_t max_q, int64_t *d_seg2, hfx_tune_report *rep) {
   hfx_plan_s &P = *B.plans[0];
+  Work &W = B.w;
   const int r = region_of(cb, ck);
   const std::vector<int64_t> &hs = f32 ? B.h_seg32 : B.h_seg64;
   const int64_t s0 = hs[(size_t)r * 2], s1 = hs[(size_t)r * 2 + 1];
   const int64_t nq = s1 - s0;
   if (nq <= 0) return HFX_OK;
+  if (max_q > 0 && max_q < kTuneMinPrefix) max_q = kTuneMinPrefix;
   const int64_t take = (max_q > 0 && max_q < nq) ? max_q : nq;
   const int64_t seg2[2] = {s0, s0 + take};
   HIPCHK(hipMemcpyAsync(d_seg2, seg2, sizeof(seg2), hipMemcpyHostToDevice, B.stream));
@@ -1205,7 +1415,7 @@ hfx_status tune_class(Batch &B, int cb, int ck, bool f32, int64_t max_q, int64_t
   HIPCHK(hipEventCreate(&e1));
   std::vector<float> ms(cands.size(), 0.0f);
   for (size_t c = 0; c < cands.size(); ++c) {
-    SegLaunch L{B.d_sys, 1, d_seg2, f32 ? B.d_list32 : B.d_list, B.d_nprim + r, take, B.stream, cands[c].second};
+    SegLaunch L{B.d_sys, 1, d_seg2, f32 ? W.list32 : W.list, W.nprim + r, take, B.stream, cands[c].second};
     // first run loads the code object and warms the caches; the second is timed
     launch_variant(cands[c].first, cb, ck, B.op, P.coop[r], L);
     (void)hipEventRecord(e0, B.stream);
@@ -1248,37 +1458,142 @@ hfx_status tune_class(Batch &B, int cb, int ck, bool f32, int64_t max_q, int64_t
   return HFX_OK;
 }
 
+void delete_batch_locked(size_t i) {
+  Batch *B = g_batches[i];
+  (void)hipStreamSynchronize(B->stream);
+  delete B;
+  g_batches.erase(g_batches.begin() + (ptrdiff_t)i);
+}
+
 void drop_batches_of(const hfx_plan_s *P) {
   std::lock_guard<std::mutex> lk(g_batch_mu);
   for (size_t i = 0; i < g_batches.size();) {
     Batch *B = g_batches[i];
-    if (std::find(B->plans.begin(), B->plans.end(), P) != B->plans.end()) {
-      (void)hipStreamSynchronize(B->stream);
-      delete B;
-      g_batches.erase(g_batches.begin() + i);
-    } else {
+    if (std::find(B->plans.begin(), B->plans.end(), P) != B->plans.end())
+      delete_batch_locked(i);
+    else
       ++i;
-    }
   }
 }
 
 }  // namespace
+
+hfx_status plan_attach(hfx_plan_s *P) {
+  HIPCHK(hipGetDevice(&P->device));
+  Batch *B = new Batch();
+  hfx_status st = batch_init(*B, {P});
+  if (st != HFX_OK) {
+    delete B;
+    return st;
+  }
+  P->self_batch = B;
+  return HFX_OK;
+}
 
 extern "C" {
 
 hfx_status hfx_build_K(hfx_plan_t plan, const double *d_dev, double *k_dev, uint32_t flags, hfx_build_info *info) {
   if (!valid_plan(plan)) return fail(HFX_ERR_STATE, "invalid or destroyed plan");
   hfx_plan_s &P = *plan;
-  if (!P.self_batch) {
+  return run_batch(*P.self_batch, P.self_batch->w, &d_dev, &k_dev, flags, info);
+}
+
+hfx_status hfx_build_K_spin(hfx_plan_t plan, const double *d_alpha, const double *d_beta, double *k_alpha,
+                            double *k_beta, uint32_t flags, hfx_build_info *info) {
+  if (!valid_plan(plan)) return fail(HFX_ERR_STATE, "invalid or destroyed plan");
+  hfx_plan_s &P = *plan;
+  if (!P.spin_batch) {
+    if (!P.d_Dc_spin) HIPCHK(P.mem.alloc(&P.d_Dc_spin, 2 * (size_t)P.nnz_c));
+    if (!P.d_K4_spin) HIPCHK(P.mem.alloc(&P.d_K4_spin, 2 * (size_t)P.nnz_c));
     Batch *B = new Batch();
-    hfx_status st = batch_init(*B, {&P});
+    hfx_status st = batch_init(*B, {&P}, 2);
     if (st != HFX_OK) {
       delete B;
       return st;
     }
-    P.self_batch = B;
+    P.spin_batch = B;
   }
-  return run_batch(*P.self_batch, &d_dev, &k_dev, flags, info);
+  const double *d[2] = {d_alpha, d_beta};
+  double *k[2] = {k_alpha, k_beta};
+  return run_batch(*P.spin_batch, P.spin_batch->w, d, k, flags, info);
+}
+
+hfx_status hfx_kspace(hfx_plan_t plan, const double *k_dev, int32_t nk, const double *kpts_host, double alpha,
+                      double *h_dev) {
+  if (!valid_plan(plan)) return fail(HFX_ERR_STATE, "invalid or destroyed plan");
+  if (nk < 0 || (nk > 0 && (!kpts_host || !k_dev || !h_dev))) return fail(HFX_ERR_INVALID, "bad arguments");
+  if (!std::isfinite(alpha)) return fail(HFX_ERR_INVALID, "alpha must be finite");
+  for (int i = 0; i < 3 * nk; ++i)
+    if (!std::isfinite(kpts_host[i])) return fail(HFX_ERR_INVALID, "non-finite k-point");
+  hfx_plan_s &P = *plan;
+  if (!P.d_kpairs) {
+    std::vector<int4> kp;
+    std::vector<int32_t> img(P.blocks.size()), foff(P.nsh);
+    for (size_t b = 0; b < P.blocks.size(); ++b) {
+      const hfx_block &x = P.blocks[b];
+      img[b] = pack_img8(x.img[0], x.img[1], x.img[2]);
+      if (kp.empty() || kp.back().x != x.I || kp.back().y != x.J)
+        kp.push_back(make_int4(x.I, x.J, (int)b, 0));
+      kp.back().w++;
+    }
+    int64_t f = 0;
+    for (int i = 0; i < P.nsh; ++i) {
+      foff[i] = (int32_t)f;
+      f += nfunc_host(P.sh_l[i], P.sph);
+    }
+    HIPCHK(upload(P, &P.d_kpairs, kp));
+    HIPCHK(upload(P, &P.d_blk_img, img));
+    HIPCHK(upload(P, &P.d_func_off, foff));
+    P.n_kpairs = (int)kp.size();
+    P.nbf = f;
+  }
+  if (nk > P.kpts_cap) {
+    // k-points are read by the kernel after the copy below; a larger set
+    // replaces the buffer once the stream has drained
+    HIPCHK(hipStreamSynchronize(P.stream));
+    double *d = nullptr;
+    HIPCHK(P.mem.alloc(&d, 3 * (size_t)nk));
+    P.d_kpts = d;
+    P.kpts_cap = nk;
+  }
+  if (nk == 0) return HFX_OK;
+  HIPCHK(hipMemcpyAsync(P.d_kpts, kpts_host, 3 * (size_t)nk * sizeof(double), hipMemcpyHostToDevice, P.stream));
+  launch_kspace(P.ds, P.d_kpairs, P.n_kpairs, P.d_blk_img, P.d_blk_off, P.d_func_off, P.sph, k_dev, P.d_kpts, nk, P.nbf,
+                -0.5 * alpha, h_dev, P.stream);
+  HIPCHK(hipGetLastError());
+  // the k-points were copied from pageable host memory: wait so that the
+  // caller may reuse them at once
+  HIPCHK(hipStreamSynchronize(P.stream));
+  return HFX_OK;
+}
+
+hfx_status hfx_set_list_limit(hfx_plan_t plan, int64_t max_quartets) {
+  if (!valid_plan(plan)) return fail(HFX_ERR_STATE, "invalid or destroyed plan");
+  if (max_quartets < 0) return fail(HFX_ERR_INVALID, "max_quartets must be >= 0");
+  hfx_plan_s &P = *plan;
+  P.max_list = max_quartets > 0 ? max_quartets : kDefaultMaxList;
+  // batches holding the plan pick the new limit up; a longer list than the
+  // limit is dropped at the next build (and any graph holding it)
+  std::vector<Batch *> bs{P.self_batch};
+  if (P.spin_batch) bs.push_back(P.spin_batch);
+  {
+    std::lock_guard<std::mutex> lk(g_batch_mu);
+    for (Batch *B : g_batches)
+      if (std::find(B->plans.begin(), B->plans.end(), &P) != B->plans.end()) bs.push_back(B);
+  }
+  for (Batch *B : bs) {
+    (void)hipStreamSynchronize(B->stream);
+    drop_graph(*B);
+    B->max_list = INT64_MAX;
+    for (auto *Q : B->plans) B->max_list = std::min(B->max_list, Q->max_list);
+    if (B->w.cap > B->max_list || B->w.cap32 > B->max_list) {
+      if (B->w.list) (void)hipFree(B->w.list);
+      if (B->w.list32) (void)hipFree(B->w.list32);
+      B->w.list = B->w.list32 = nullptr;
+      B->w.cap = B->w.cap32 = 0;
+    }
+  }
+  return HFX_OK;
 }
 
 hfx_status hfx_build_K_subset(hfx_plan_t plan, const double *d_dev, double *k_dev, const uint64_t *quartets_host,
@@ -1321,7 +1636,7 @@ hfx_status hfx_build_K_subset(hfx_plan_t plan, const double *d_dev, double *k_de
   HIPCHK(hipMemcpyAsync(d_seg, seg.data(), seg.size() * 8, hipMemcpyHostToDevice, st));
   launch_zero_u64(d_np, kNQuartetClass, st);
   launch_zero_u64(P.d_pglob, 1, st);
-  launch_density(P.ds, (int64_t)P.blocks.size(), P.d_blk_IJ, P.d_blk_off, P.d_partner, P.d_canon, P.sph, d_dev, P.d_Dc,
+  launch_density(P.ds, (int64_t)P.blocks.size(), P.d_blk_IJ, P.d_blk_off, P.d_partner, P.d_canon, P.sph, d_dev, P.d_Dc, false,
                  st);
   launch_zero(P.d_K4, P.nnz_c, st);
   for (int cb = 0; cb < kNPairClass; ++cb)
@@ -1333,8 +1648,10 @@ hfx_status hfx_build_K_subset(hfx_plan_t plan, const double *d_dev, double *k_de
       launch_variant(P.kern[r], cb, ck, P.op, P.coop[r], L);
     }
   launch_finalize(P.ds, (int64_t)P.blocks.size(), P.d_blk_IJ, P.d_blk_off, P.d_partner, P.sph, P.d_K4, k_dev, st);
-  HIPCHK(hipGetLastError());
-  HIPCHK(hipStreamSynchronize(st));
+  hipError_t e = hipGetLastError();
+  if (e == hipSuccess) e = hipStreamSynchronize(st);
+  mem.release();
+  HIPCHK(e);
   return HFX_OK;
 }
 
@@ -1346,29 +1663,21 @@ hfx_status hfx_screen_count(hfx_plan_t plan, const double *d_dev, int64_t *n64, 
     hfx_status st = run_schwarz(P);
     if (st != HFX_OK) return st;
   }
-  if (!P.self_batch) {
-    Batch *B = new Batch();
-    hfx_status st = batch_init(*B, {&P});
-    if (st != HFX_OK) {
-      delete B;
-      return st;
-    }
-    P.self_batch = B;
-  }
   Batch &B = *P.self_batch;
+  Work &W = B.w;
   launch_zero_u64(P.d_pglob, 1, B.stream);
-  launch_density(P.ds, (int64_t)P.blocks.size(), P.d_blk_IJ, P.d_blk_off, P.d_partner, P.d_canon, P.sph, d_dev, P.d_Dc,
+  launch_density(P.ds, (int64_t)P.blocks.size(), P.d_blk_IJ, P.d_blk_off, P.d_partner, P.d_canon, P.sph, d_dev, P.d_Dc, false,
                  B.stream);
-  launch_zero_i32(B.d_err, 2, B.stream);
+  launch_zero_i32(W.err, 2, B.stream);
   int64_t tot[2] = {0, 0};
   for (int pass = 0; pass < (B.mixed ? 2 : 1); ++pass) {
     const int mode = B.mixed ? 1 + pass : 0;
-    launch_screen(B.d_sys, B.d_items, B.nitems, B.d_counts, B.d_offsets, nullptr, 0, B.d_err, false, mode, B.stream);
-    HIPCHK(scan_counts(B.d_counts, B.d_offsets, B.nitems, B.d_scan_tmp, B.stream));
-    HIPCHK(hipMemcpyAsync(&tot[pass], B.d_offsets + B.nitems, sizeof(int64_t), hipMemcpyDeviceToHost, B.stream));
+    launch_screen(B.d_sys, B.d_items, B.nitems, W.counts, W.offsets, nullptr, 0, 0, W.err, false, mode, B.stream);
+    HIPCHK(scan_counts(W.counts, W.offsets, B.nitems, W.tiles, B.stream));
+    HIPCHK(hipMemcpyAsync(&tot[pass], W.offsets + B.nitems, sizeof(int64_t), hipMemcpyDeviceToHost, B.stream));
   }
   HIPCHK(hipStreamSynchronize(B.stream));
-  hfx_status st = check_err(B, nullptr);
+  hfx_status st = check_err(B, W, nullptr);
   if (st != HFX_OK) return st;
   *n64 = tot[0];
   if (n32) *n32 = tot[1];
@@ -1388,6 +1697,8 @@ hfx_status hfx_autotune(hfx_plan_t plan, const double *d_dev, double *k_dev, int
   hfx_status st = hfx_build_K(plan, d_dev, k_dev, HFX_SYNC, nullptr);
   if (st != HFX_OK) return st;
   Batch &B = *P.self_batch;
+  if (B.n_chunks > 0)
+    return fail(HFX_ERR_UNSUPPORTED, "autotune needs the whole quartet list: raise the plan's list limit");
   int64_t *d_seg2 = nullptr;
   HIPCHK(hipMalloc((void **)&d_seg2, 2 * sizeof(int64_t)));
   for (int cb = 0; cb < kNPairClass && st == HFX_OK; ++cb)
@@ -1439,17 +1750,22 @@ hfx_status hfx_build_K_multi(int32_t n, const hfx_plan_t *plans, const double *c
         return st;
       }
       std::lock_guard<std::mutex> lk(g_batch_mu);
-      g_batches.push_back(B);
-      // keep the cache bounded
-      if (g_batches.size() > 64) {
-        Batch *old = g_batches.front();
-        (void)hipStreamSynchronize(old->stream);
-        delete old;
-        g_batches.erase(g_batches.begin());
+      // a plan belongs to at most one cached batch: a new plan list (the
+      // serving mix changes from step to step) replaces every cached batch
+      // it shares a plan with, so their lists do not pile up on the device
+      for (size_t i = 0; i < g_batches.size();) {
+        bool shares = false;
+        for (auto *P : ps) shares |= std::find(g_batches[i]->plans.begin(), g_batches[i]->plans.end(), P) !=
+                                     g_batches[i]->plans.end();
+        if (shares)
+          delete_batch_locked(i);
+        else
+          ++i;
       }
+      g_batches.push_back(B);
     }
     hfx_build_info sub;
-    hfx_status st = run_batch(*B, ds.data(), ks.data(), flags, info ? &sub : nullptr);
+    hfx_status st = run_batch(*B, B->w, ds.data(), ks.data(), flags, info ? &sub : nullptr);
     if (st != HFX_OK) return st;
     if (info) {
       info->n_quartets += sub.n_quartets;
@@ -1461,6 +1777,7 @@ hfx_status hfx_build_K_multi(int32_t n, const hfx_plan_t *plans, const double *c
       info->ms_eri += sub.ms_eri;
       info->ms_finalize += sub.ms_finalize;
       info->ms_total += sub.ms_total;
+      info->n_chunks += sub.n_chunks;
       for (int r = 0; r < HFX_N_CLASSES; ++r) {
         info->n_quartets_class[r] += sub.n_quartets_class[r];
         info->ms_class[r] += sub.ms_class[r];
@@ -1487,10 +1804,12 @@ hfx_status hfx_export(hfx_plan_t plan, int32_t what, void *host, int64_t *n) {
     case 1:
     case 5: {
       const bool f32 = what == 5;
-      *n = B ? (f32 ? B->nq32 : B->nq64) : 0;
+      if (B->have_counts && B->n_chunks > 0)
+        return fail(HFX_ERR_STATE, "the last build evaluated its quartet list in chunks: no whole list to export");
+      *n = B->have_counts ? (f32 ? B->nq32 : B->nq64) : 0;
       if (host && *n) {
         HIPCHK(hipStreamSynchronize(P.stream));
-        HIPCHK(hipMemcpy(host, f32 ? B->d_list32 : B->d_list, *n * 8, hipMemcpyDeviceToHost));
+        HIPCHK(hipMemcpy(host, f32 ? B->w.list32 : B->w.list, *n * 8, hipMemcpyDeviceToHost));
       }
       return HFX_OK;
     }
@@ -1530,6 +1849,8 @@ hfx_status hfx_plan_destroy(hfx_plan_t plan) {
   (void)hipStreamSynchronize(plan->stream);
   delete plan->self_batch;
   plan->self_batch = nullptr;
+  delete plan->spin_batch;
+  plan->spin_batch = nullptr;
   plan->mem.release();
   plan->magic = 0;
   delete plan;

@@ -146,8 +146,10 @@ struct DevSys {
   double fp32_cut[kNQuartetClass];
   const double *boys;     // kBoysRows x kBoysCols
   // per-build state of this plan
-  const double *Dc;       // Cartesian density blocks
-  double *K4;             // Cartesian K accumulator (row-first contributions)
+  const double *Dc;       // Cartesian density blocks (spin s at Dc + s * spin_stride)
+  double *K4;             // Cartesian K accumulator (row-first contributions), same layout
+  int32_t nspin;          // 1, or 2 for a collinear-spin build (both spins share every integral)
+  int64_t spin_stride;    // Cartesian values per spin
   int32_t class_start[kNPairClass + 1];  // unique pairs of class c: [class_start[c], class_start[c+1])
 };
 

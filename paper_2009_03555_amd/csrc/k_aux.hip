@@ -162,7 +162,7 @@ __device__ __forceinline__ double tmat(int l, int sph, int m, int a) {
 __global__ void density_kernel(DevSys s, int64_t nblk, const int2 *__restrict__ blk_IJ,
                                const int64_t *__restrict__ blk_off, const int32_t *__restrict__ partner,
                                const uint8_t *__restrict__ canon, int sph, const double *__restrict__ D,
-                               double *__restrict__ Dc) {
+                               double *__restrict__ Dc, int accumulate) {
   const int64_t b = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (b >= nblk) return;
   const int2 ij = blk_IJ[b];
@@ -195,6 +195,8 @@ __global__ void density_kernel(DevSys s, int64_t nblk, const int2 *__restrict__ 
       pm = fmax(pm, fabs(v));
     }
   if (canon[b]) {
+    // a second spin density keeps the larger block maximum of the two
+    if (accumulate) pm = fmax(pm, s.pmax[b]);
     s.pmax[b] = pm;
     s.pmax[partner[b]] = pm;
     atomicMax(s.pmax_global, (unsigned long long)__double_as_longlong(pm));
@@ -203,10 +205,10 @@ __global__ void density_kernel(DevSys s, int64_t nblk, const int2 *__restrict__ 
 
 void launch_density(const DevSys &s, int64_t nblk, const int2 *blk_IJ, const int64_t *blk_off,
                     const int32_t *partner, const uint8_t *canon, int spherical, const double *D, double *Dc,
-                    hipStream_t st) {
+                    bool accumulate, hipStream_t st) {
   if (nblk <= 0) return;
   hipLaunchKernelGGL(density_kernel, dim3((unsigned)((nblk + 255) / 256)), dim3(256), 0, st, s, nblk, blk_IJ,
-                     blk_off, partner, canon, spherical, D, Dc);
+                     blk_off, partner, canon, spherical, D, Dc, accumulate ? 1 : 0);
 }
 
 // ------------------------------------------------------------ finalize
@@ -347,8 +349,8 @@ __global__ __launch_bounds__(256) void screen_kernel(const DevSys *__restrict__ 
                                                      const int4 *__restrict__ items, int64_t nitems,
                                                      int32_t *__restrict__ counts,
                                                      const int64_t *__restrict__ offsets,
-                                                     uint64_t *__restrict__ out, int64_t cap, int32_t *err,
-                                                     int fill, int mode) {
+                                                     uint64_t *__restrict__ out, int64_t base, int64_t cap,
+                                                     int32_t *err, int fill, int mode) {
   const int lane = threadIdx.x & 63;
   const int64_t item = (int64_t)blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6);
   if (item >= nitems) return;  // whole wave leaves together
@@ -364,7 +366,7 @@ __global__ __launch_bounds__(256) void screen_kernel(const DevSys *__restrict__ 
   const double Qp = s.pr_Q[p];
   const double cut32 = s.fp32_cut[r];
   const double pglob = __longlong_as_double((long long)*s.pmax_global);
-  int64_t running = fill ? offsets[item] : 0;
+  int64_t running = fill ? offsets[item] - base : 0;
   for (int qt = q0; qt < q1; qt += 64) {
     const int q = qt + lane;
     int cnt = 0;
@@ -397,27 +399,28 @@ __global__ __launch_bounds__(256) void screen_kernel(const DevSys *__restrict__ 
 }
 
 void launch_screen(const DevSys *sys, const int4 *items, int64_t nitems, int32_t *counts, const int64_t *offsets,
-                   uint64_t *out, int64_t cap, int32_t *err, bool fill, int mode, hipStream_t st) {
+                   uint64_t *out, int64_t base, int64_t cap, int32_t *err, bool fill, int mode, hipStream_t st) {
   if (nitems <= 0) return;
   const int64_t blocks = (nitems + 3) / 4;
   hipLaunchKernelGGL(screen_kernel, dim3((unsigned)blocks), dim3(256), 0, st, sys, items, nitems, counts, offsets,
-                     out, cap, err, fill ? 1 : 0, mode);
+                     out, base, cap, err, fill ? 1 : 0, mode);
 }
 
 __global__ void gather_bounds_kernel(const int64_t *__restrict__ offsets, const int64_t *__restrict__ seg_items,
-                                     int64_t *__restrict__ seg, int n, int64_t cap) {
+                                     int64_t *__restrict__ seg, int n, int64_t lo, int64_t hi) {
   const int k = blockIdx.x * blockDim.x + threadIdx.x;
   if (k < n) {
-    const int64_t v = offsets[seg_items[k]];
-    seg[k] = v < cap ? v : cap;
+    int64_t v = offsets[seg_items[k]];
+    v = v < lo ? lo : (v > hi ? hi : v);
+    seg[k] = v - lo;
   }
 }
 
-void launch_gather_bounds(const int64_t *offsets, const int64_t *seg_items, int64_t *seg, int n, int64_t cap,
-                          hipStream_t st) {
+void launch_gather_bounds(const int64_t *offsets, const int64_t *seg_items, int64_t *seg, int n, int64_t lo,
+                          int64_t hi, hipStream_t st) {
   if (n <= 0) return;
   hipLaunchKernelGGL(gather_bounds_kernel, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, offsets, seg_items,
-                     seg, n, cap);
+                     seg, n, lo, hi);
 }
 
 __global__ void zero_i32_kernel(int32_t *p, int64_t n) {
@@ -509,6 +512,63 @@ hipError_t scan_counts(const int32_t *counts, int64_t *offsets, int64_t n, int64
   hipLaunchKernelGGL(scan_tiles, dim3(1), dim3(kScanThreads), 0, st, tiles, nt);
   hipLaunchKernelGGL(scan_apply, dim3((unsigned)nt), dim3(kScanThreads), 0, st, counts, n, tiles, offsets);
   return hipGetLastError();
+}
+
+}  // namespace hfx
+
+namespace hfx {
+
+// ------------------------------------------------------- k-space assembly
+// H(k)_{mu nu} = scale * sum_G K^G_{mu nu} exp(i k . (T_G + r_nu - r_mu)) for
+// every k-point, dense complex (re, im interleaved) [nk][nbf][nbf].  One
+// thread per (k, shell pair (I, J), element): it walks the pattern blocks
+// (I, J, G) of the pair, which are contiguous, so no two threads write one
+// entry.  Entries of shell pairs outside the pattern are zeroed by the
+// caller.
+__global__ __launch_bounds__(64) void kspace_kernel(DevSys s, const int4 *__restrict__ pairs, int npairs,
+                                                    const int32_t *__restrict__ blk_img,
+                                                    const int64_t *__restrict__ blk_off,
+                                                    const int32_t *__restrict__ func_off, int sph,
+                                                    const double *__restrict__ K, const double *__restrict__ kpts,
+                                                    int nk, int64_t nbf, double scale, double *__restrict__ H) {
+  const int p = blockIdx.x;
+  const int k = blockIdx.y;
+  if (p >= npairs || k >= nk) return;
+  const int4 pr = pairs[p];  // I, J, first block, block count
+  const int I = pr.x, J = pr.y;
+  const int ni = nfunc_dev(s.sh_l[I], sph), nj = nfunc_dev(s.sh_l[J], sph);
+  const int e = threadIdx.x;
+  if (e >= ni * nj) return;
+  const double kx = kpts[3 * k], ky = kpts[3 * k + 1], kz = kpts[3 * k + 2];
+  const double dx = s.sh_xyz[3 * J] - s.sh_xyz[3 * I], dy = s.sh_xyz[3 * J + 1] - s.sh_xyz[3 * I + 1],
+               dz = s.sh_xyz[3 * J + 2] - s.sh_xyz[3 * I + 2];
+  double re = 0.0, im = 0.0;
+  for (int b = pr.z; b < pr.z + pr.w; ++b) {
+    int n1, n2, n3;
+    unpack_img8(blk_img[b], n1, n2, n3);
+    const double tx = n1 * s.lat[0] + n2 * s.lat[3] + n3 * s.lat[6] + dx;
+    const double ty = n1 * s.lat[1] + n2 * s.lat[4] + n3 * s.lat[7] + dy;
+    const double tz = n1 * s.lat[2] + n2 * s.lat[5] + n3 * s.lat[8] + dz;
+    double sn, cs;
+    sincos(kx * tx + ky * ty + kz * tz, &sn, &cs);
+    const double v = K[blk_off[b] + e];
+    re = fma(v, cs, re);
+    im = fma(v, sn, im);
+  }
+  const int m = e / nj, n = e - m * nj;
+  const int64_t row = func_off[I] + m, col = func_off[J] + n;
+  double *h = H + 2 * (((int64_t)k * nbf + row) * nbf + col);
+  h[0] = scale * re;
+  h[1] = scale * im;
+}
+
+void launch_kspace(const DevSys &s, const int4 *pairs, int npairs, const int32_t *blk_img, const int64_t *blk_off,
+                   const int32_t *func_off, int sph, const double *K, const double *kpts, int nk, int64_t nbf,
+                   double scale, double *H, hipStream_t st) {
+  launch_zero(H, 2 * (int64_t)nk * nbf * nbf, st);
+  if (npairs <= 0 || nk <= 0) return;
+  hipLaunchKernelGGL(kspace_kernel, dim3((unsigned)npairs, (unsigned)nk), dim3(64), 0, st, s, pairs, npairs, blk_img,
+                     blk_off, func_off, sph, K, kpts, nk, nbf, scale, H);
 }
 
 }  // namespace hfx

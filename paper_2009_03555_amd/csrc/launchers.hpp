@@ -88,27 +88,38 @@ void launch_schwarz(int cb, int op, const DevSys &s, int p0, int p1, hipStream_t
 void launch_zero_i32(int32_t *p, int64_t n, hipStream_t st);
 
 // D (boundary basis) -> D_cart and P_max per block (canonical block decides,
-// partner copies); global max into s.pmax_global.
+// partner copies); global max into s.pmax_global.  accumulate: P_max becomes
+// the larger of its current value and this density's (second spin).
 void launch_density(const DevSys &s, int64_t nblk, const int2 *blk_IJ, const int64_t *blk_off,
                     const int32_t *partner, const uint8_t *canon, int spherical, const double *D, double *Dc,
-                    hipStream_t st);
+                    bool accumulate, hipStream_t st);
 // K_cart = K4 + K4^T (image flip), K = T K_cart T^T written in the boundary basis.
 void launch_finalize(const DevSys &s, int64_t nblk, const int2 *blk_IJ, const int64_t *blk_off,
                      const int32_t *partner, int spherical, const double *K4, double *K, hipStream_t st);
 void launch_zero(double *p, int64_t n, hipStream_t st);
+// H(k) = scale sum_G K^G exp(i k.(T_G + r_J - r_I)), dense complex [nk][nbf][nbf]
+// (zeroed first); pairs: (I, J, first pattern block, block count) of every
+// shell pair of the pattern; blk_img: packed image (8 bits per component)
+// of each block; func_off: first boundary function of each shell.
+void launch_kspace(const DevSys &s, const int4 *pairs, int npairs, const int32_t *blk_img, const int64_t *blk_off,
+                   const int32_t *func_off, int sph, const double *K, const double *kpts, int nk, int64_t nbf,
+                   double scale, double *H, hipStream_t st);
 void launch_zero_u64(unsigned long long *p, int64_t n, hipStream_t st);
 // Screening over fused work items (region, bra pair, plan), one wave per
 // item.  mode: 0 every kept quartet, 1 only Q_IJ*Q_KL >= the region's
 // fp32_cut (FP64 list), 2 only Q_IJ*Q_KL < fp32_cut (FP32 list).  Count pass
-// writes counts[item]; fill pass writes at offsets[item] and never at or
-// beyond cap (sets err bit 2).
+// writes counts[item]; fill pass writes item's quartets at offsets[item] -
+// base and never at or beyond cap (sets err bit 2).  A chunk of the list is
+// filled by passing the chunk's first item (items + i0, offsets + i0), its
+// item count and base = offsets[i0].
 void launch_screen(const DevSys *sys, const int4 *items, int64_t nitems, int32_t *counts, const int64_t *offsets,
-                   uint64_t *out, int64_t cap, int32_t *err, bool fill, int mode, hipStream_t st);
-// seg[k] = min(offsets[seg_items[k]], cap), k < n: class-segment bounds on
-// the device, clamped to the list capacity so that the ERI kernels of a
-// replayed graph never read past the list when the screened count overflows
-void launch_gather_bounds(const int64_t *offsets, const int64_t *seg_items, int64_t *seg, int n, int64_t cap,
-                          hipStream_t st);
+                   uint64_t *out, int64_t base, int64_t cap, int32_t *err, bool fill, int mode, hipStream_t st);
+// seg[k] = clamp(offsets[seg_items[k]], lo, hi) - lo, k < n: class-segment
+// bounds on the device of the list part [lo, hi) held in the list buffer
+// (lo = 0, hi = capacity for a whole list: a replayed graph whose screened
+// count overflows never reads past the list)
+void launch_gather_bounds(const int64_t *offsets, const int64_t *seg_items, int64_t *seg, int n, int64_t lo,
+                          int64_t hi, hipStream_t st);
 // exclusive prefix sum of int32 counts into int64 offsets (n+1 entries)
 // tiles: device scratch of at least (n + 1023) / 1024 entries
 hipError_t scan_counts(const int32_t *counts, int64_t *offsets, int64_t n, int64_t *tiles, hipStream_t st);

@@ -58,7 +58,8 @@ class hfx_build_info(ctypes.Structure):
                 ("flops", ctypes.c_double), ("ms_density", ctypes.c_double),
                 ("ms_screen", ctypes.c_double), ("ms_eri", ctypes.c_double),
                 ("ms_finalize", ctypes.c_double), ("ms_total", ctypes.c_double),
-                ("ms_class", ctypes.c_double * N_CLASSES), ("flops_class", ctypes.c_double * N_CLASSES)]
+                ("ms_class", ctypes.c_double * N_CLASSES), ("flops_class", ctypes.c_double * N_CLASSES),
+                ("n_chunks", ctypes.c_int64)]
 
     def as_dict(self):
         d = {}
@@ -121,9 +122,14 @@ def lib():
         L.hfx_autotune.argtypes = [vp, vp, vp, ctypes.c_int64, ctypes.POINTER(hfx_tune_report)]
         L.hfx_screen_count.argtypes = [vp, vp, ctypes.POINTER(ctypes.c_int64), ctypes.POINTER(ctypes.c_int64)]
         L.hfx_build_K_subset.argtypes = [vp, vp, vp, ctypes.POINTER(ctypes.c_uint64), ctypes.c_int64]
+        L.hfx_set_list_limit.argtypes = [vp, ctypes.c_int64]
+        dpp = ctypes.POINTER(ctypes.c_double)
+        L.hfx_nao2gto_fit.argtypes = [ctypes.c_int32, ctypes.c_int32, dpp, dpp, ctypes.c_int32, dpp, dpp, dpp]
+        L.hfx_kspace.argtypes = [vp, vp, ctypes.c_int32, ctypes.POINTER(ctypes.c_double), ctypes.c_double, vp]
+        L.hfx_build_K_spin.argtypes = [vp, vp, vp, vp, vp, ctypes.c_uint32, ctypes.POINTER(hfx_build_info)]
         for name in ("hfx_footprint", "hfx_plan", "hfx_pattern", "hfx_schwarz", "hfx_build_K",
                      "hfx_build_K_multi", "hfx_export", "hfx_plan_destroy", "hfx_autotune", "hfx_screen_count",
-                     "hfx_build_K_subset"):
+                     "hfx_build_K_subset", "hfx_set_list_limit", "hfx_build_K_spin", "hfx_kspace", "hfx_nao2gto_fit"):
             getattr(L, name).restype = ctypes.c_int
         _lib = L
     return _lib
@@ -222,6 +228,31 @@ class Plan:
                                  ctypes.byref(inf) if inf is not None else None))
         return inf.as_dict() if inf is not None else None
 
+    def build_K_spin(self, D_alpha, D_beta, K_alpha, K_beta, flags: int = 0, info: bool = False):
+        """``hfx_build_K_spin``: K of both spin densities from one ERI
+        evaluation (collinear spin)."""
+        inf = hfx_build_info() if info else None
+        _check(lib().hfx_build_K_spin(self._h, ctypes.c_void_p(_ptr(D_alpha)), ctypes.c_void_p(_ptr(D_beta)),
+                                      ctypes.c_void_p(_ptr(K_alpha)), ctypes.c_void_p(_ptr(K_beta)),
+                                      ctypes.c_uint32(flags), ctypes.byref(inf) if inf is not None else None))
+        return inf.as_dict() if inf is not None else None
+
+    def kspace(self, K, kpts, alpha: float, H):
+        """``hfx_kspace``: H(k) = -(alpha/2) sum_G K^G exp(i k.(T_G + r_nu - r_mu))
+        into H (complex128 device tensor [nk, nbf, nbf], or float64 with a
+        trailing dimension of 2)."""
+        k = np.ascontiguousarray(kpts, dtype=np.float64).reshape(-1, 3)
+        if not H.is_contiguous():
+            raise ValueError("H must be contiguous")
+        _check(lib().hfx_kspace(self._h, ctypes.c_void_p(_ptr(K)), len(k),
+                                k.ctypes.data_as(ctypes.POINTER(ctypes.c_double)), ctypes.c_double(alpha),
+                                ctypes.c_void_p(H.data_ptr())))
+
+    def set_list_limit(self, max_quartets: int):
+        """``hfx_set_list_limit``: longest quartet list a build holds at once
+        (longer screened lists run in chunks); 0 restores the default."""
+        _check(lib().hfx_set_list_limit(self._h, ctypes.c_int64(int(max_quartets))))
+
     def build_K_subset(self, D, K, quartets: np.ndarray):
         """``hfx_build_K_subset``: K from the given unique quartets only
         (uint64 encoding of export(1))."""
@@ -278,6 +309,22 @@ def build_K_multi(plans: Sequence[Plan], Ds, Ks, flags: int = 0, info: bool = Fa
     _check(lib().hfx_build_K_multi(n, hs, ds, ks, ctypes.c_uint32(flags),
                                    ctypes.byref(inf) if inf is not None else None))
     return inf.as_dict() if inf is not None else None
+
+
+def nao2gto_fit(l: int, r, radial, n_gto: int):
+    """``hfx_nao2gto_fit``: (exponents, raw coefficients, relative rms) of
+    the GTO contraction fitted to the radial function on grid r."""
+    r = np.ascontiguousarray(r, dtype=np.float64)
+    R = np.ascontiguousarray(radial, dtype=np.float64)
+    if r.shape != R.shape:
+        raise ValueError("r and radial differ in length")
+    ex = np.zeros(n_gto)
+    co = np.zeros(n_gto)
+    rms = ctypes.c_double(0.0)
+    dp = ctypes.POINTER(ctypes.c_double)
+    _check(lib().hfx_nao2gto_fit(int(l), len(r), r.ctypes.data_as(dp), R.ctypes.data_as(dp), int(n_gto),
+                                 ex.ctypes.data_as(dp), co.ctypes.data_as(dp), ctypes.byref(rms)))
+    return ex, co, float(rms.value)
 
 
 def unpack_quartets(q: np.ndarray) -> np.ndarray:

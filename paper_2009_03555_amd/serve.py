@@ -164,12 +164,19 @@ class HipExecutor:
     """Device executor: one ``hfx`` plan per request, densities of all its SCF
     iterations and its K resident on the device, one fused build per step.
 
-    Footprint = the plan's static device memory (``hfx_footprint``) + the
-    densities and K + the quartet lists, sized from the screened count of the
-    first density (``hfx_screen_count``) with 25% headroom.  Sizing the head
-    of the queue makes its plan, which waits (outside the accounting) until
-    the request is admitted.  Requests whose static part alone exceeds the
-    limit are rejected by the server."""
+    Footprint = the plan's device memory (``hfx_footprint``: its tables, its
+    own one-plan batch and its share of a fused batch) + the densities and K
+    (one allocation, rounded up to the 2 MiB segments of torch's caching
+    allocator) + the quartet lists, sized from the screened count of the
+    first density (``hfx_screen_count``) with 25% headroom.  Sizing a
+    request makes a probe plan and uploads its first density; both are
+    released before the request can be admitted, so that nothing of a
+    waiting request stays on the device.  Requests whose static part alone
+    exceeds the limit are rejected by the server.  ``peak_device_bytes``: the
+    largest device memory in use (hipMemGetInfo, through torch) seen after a
+    step, for checking the accounting against the device."""
+
+    SEGMENT = 2 << 20
 
     def __init__(self, keep_results: bool = True, flags: Optional[int] = None, list_headroom: float = 1.25):
         from paper_2009_03555_amd import hfx
@@ -180,15 +187,20 @@ class HipExecutor:
         self.flags = hfx.HFX_SYNC if flags is None else flags
         self.headroom = list_headroom
         self._fp = {}
-        self._pending = {}
+        self._nq = {}
+        self.peak_device_bytes = 0
 
-    def _densities(self, req: ServeRequest, blocks):
+    def _densities(self, req: ServeRequest, blocks, iterations):
         import systems
         out = []
-        for it in range(req.n_iter):
+        for it in iterations:
             vals = systems.perturb_density(req.system, np.asarray(blocks, dtype=np.int64), it)
             out.append(np.concatenate([v.ravel() for v in vals]) if vals else np.zeros(0))
         return out
+
+    def device_bytes_in_use(self) -> int:
+        free, total = self.torch.cuda.mem_get_info()
+        return int(total - free)
 
     def static_footprint(self, req: ServeRequest) -> int:
         dev, _ = self.hfx.hfx_footprint(req.system)
@@ -198,22 +210,28 @@ class HipExecutor:
         if req.rid in self._fp:
             return self._fp[req.rid]
         dev, per_q = self.hfx.hfx_footprint(req.system)
-        # the list part is known only after screening; a plan is made once
-        # here and kept for admit() (its static memory is part of dev)
+        # the list part is known only after screening: a probe plan counts
+        # the quartets of the first density, then goes away
         plan = self.hfx.Plan(req.system)
-        D = self._densities(req, plan.blocks)
-        Dd = [self.torch.from_numpy(d).cuda() for d in D]
-        n64, n32 = plan.screen_count(Dd[0])
-        need = dev + 8 * plan.nnz * (req.n_iter + 1) + int(self.headroom * per_q * (n64 + n32))
+        D0 = self.torch.from_numpy(self._densities(req, plan.blocks, [0])[0]).cuda()
+        n64, n32 = plan.screen_count(D0)
+        nnz = plan.nnz
+        plan.destroy()
+        del D0
+        dk = -(-8 * nnz * (req.n_iter + 1) // self.SEGMENT) * self.SEGMENT
+        need = dev + dk + int(self.headroom * per_q * (n64 + n32))
         self._fp[req.rid] = need
-        self._pending[req.rid] = (plan, Dd, n64 + n32)
+        self._nq[req.rid] = n64 + n32
         return need
 
     def admit(self, req: ServeRequest):
         self.footprint(req)
-        plan, Dd, nq = self._pending.pop(req.rid)
-        K = self.torch.zeros_like(Dd[0])
-        return {"req": req, "plan": plan, "D": Dd, "K": K, "it": 0, "quartets": nq}
+        plan = self.hfx.Plan(req.system)
+        D = self._densities(req, plan.blocks, range(req.n_iter))
+        # densities of every iteration and K in one device allocation
+        buf = self.torch.zeros((req.n_iter + 1, plan.nnz), dtype=self.torch.float64, device="cuda")
+        buf[: req.n_iter] = self.torch.from_numpy(np.stack(D)).cuda()
+        return {"req": req, "plan": plan, "buf": buf, "it": 0, "quartets": self._nq.pop(req.rid)}
 
     def cost(self, state) -> float:
         """work of one build of the request: its screened quartet count"""
@@ -221,16 +239,17 @@ class HipExecutor:
 
     def step(self, states) -> None:
         plans = [s["plan"] for s in states]
-        Ds = [s["D"][s["it"]] for s in states]
-        Ks = [s["K"] for s in states]
+        Ds = [s["buf"][s["it"]] for s in states]
+        Ks = [s["buf"][-1] for s in states]
         self.hfx.build_K_multi(plans, Ds, Ks, flags=self.flags)
         self.torch.cuda.synchronize()
+        self.peak_device_bytes = max(self.peak_device_bytes, self.device_bytes_in_use())
         for s in states:
             s["it"] += 1
 
     def retire(self, state):
-        out = state["K"].cpu().numpy() if self.keep else None
+        out = state["buf"][-1].cpu().numpy() if self.keep else None
         state["plan"].destroy()
         self._fp.pop(state["req"].rid, None)
-        state["D"] = state["K"] = None
+        state["buf"] = None
         return out

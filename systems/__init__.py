@@ -20,4 +20,6 @@ from .generate import (  # noqa: F401
     splitmix64,
     hash_uniform,
     nfunc,
+    nao_radial,
+    nao_basis,
 )

@@ -369,3 +369,28 @@ def density_blocks(system: System, blocks: np.ndarray, iteration: int = 0,
 def perturb_density(system: System, blocks: np.ndarray, iteration: int) -> List[np.ndarray]:
     """Density of SCF iteration ``iteration`` (0 = initial) of a request."""
     return density_blocks(system, blocks, iteration=iteration)
+
+
+# --------------------------------------------------------------------------
+# synthetic numerical atomic orbitals (radial tables with a strict cutoff)
+# --------------------------------------------------------------------------
+def nao_radial(l: int, zeta: float, r_cut: float, n_r: int = 400) -> Tuple[np.ndarray, np.ndarray]:
+    """A radial table shaped like a confined numerical atomic orbital:
+    R(r) = r^l exp(-zeta r) (1 - (r / r_cut)^2)^2 for r < r_cut and 0 beyond,
+    on n_r uniform points of [0, r_cut] (the real NAO and pseudopotential
+    files of the paper's systems are not available)."""
+    r = np.linspace(0.0, r_cut, n_r)
+    R = r ** l * np.exp(-zeta * r) * (1.0 - (r / r_cut) ** 2) ** 2
+    return r, R
+
+
+def nao_basis(seed: int, shells=(0, 0, 1, 1, 2)) -> List[Tuple[int, float, float]]:
+    """Seeded (l, zeta, r_cut) of an element's numerical orbitals: zeta
+    log-uniform in [0.6, 2.5] bohr^-1, r_cut uniform in [5, 8] bohr."""
+    rng = np.random.Generator(np.random.PCG64(seed))
+    out = []
+    for l in shells:
+        zeta = float(np.exp(rng.uniform(np.log(0.6), np.log(2.5))))
+        rc = float(rng.uniform(5.0, 8.0))
+        out.append((int(l), zeta, rc))
+    return out

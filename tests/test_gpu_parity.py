@@ -327,21 +327,106 @@ def test_subset_rejects_bad_quartets(cell):
         cell.plan.build_K_subset(cell.Dd, K, np.array([np.uint64(1) << np.uint64(23)], dtype=np.uint64))
 
 
+@pytest.mark.parametrize("which", ["c1", "cell"])
+def test_quartet_list_exact_with_the_gpus_screening_inputs(which, c1, cell):
+    """The oracle's predicate fed the GPU's exported Schwarz factors and
+    P_max selects exactly the GPU's list (as a set of canonical orbits): the
+    quartet selection is bit-identical, with no threshold window."""
+    c = c1 if which == "c1" else cell
+    o = oracle.Oracle(c.s)
+    o.set_density(c.D)
+    o.set_q(c.plan.schwarz())
+    o.set_pmax(c.plan.export(0))
+    gl = hfx.unpack_quartets(c.plan.export(1))
+    gk = key_set(canonical_keys(gpu_quartet_instances(gl, c.plan.export(2))))
+    rows, _ = o.quartets(gR=3)
+    ok = key_set(canonical_keys(oracle_quartet_instances(rows)))
+    assert gk == ok, (len(gk - ok), len(ok - gk))
+    assert len(gk) == len(gl)
+
+
+def _region(ls, I, J, K, L):
+    def pc(a, b):
+        a, b = max(a, b), min(a, b)
+        return 0 if a == 0 else (1 + b if a == 1 else 3 + b)
+    p, q = pc(ls[I], ls[J]), pc(ls[K], ls[L])
+    cb, ck = max(p, q), min(p, q)
+    return cb * (cb + 1) // 2 + ck
+
+
+def test_full_size_list_on_sampled_bra_pairs():
+    """The 64-atom periodic diamond workload at full size: for a seeded
+    sample of shell pairs (three of each pair class), the orbits of the
+    GPU's list containing the pair equal the oracle's kept orbits with that
+    bra pair (the oracle screening with the GPU's Q and P_max: exact)."""
+    s = systems.config2_diamond()
+    plan = hfx.Plan(s)
+    D = _density(s, plan.blocks)
+    Dd = torch.from_numpy(D).to(DEV)
+    Kd = torch.zeros_like(Dd)
+    info = plan.build_K(Dd, Kd, flags=hfx.HFX_SYNC, info=True)
+    qb = plan.schwarz()
+    pm = plan.export(0)
+    pairs = plan.export(2)
+    rng = np.random.default_rng(2024)
+    pick = np.concatenate([rng.choice(np.flatnonzero(pairs[:, 5] == c), size=3, replace=False) for c in range(6)])
+    lst = plan.export(1)
+    assert len(lst) == info["n_quartets"]
+    sel = np.zeros(len(pairs), dtype=bool)
+    sel[pick] = True
+    keep = []
+    step = 1 << 26
+    for a in range(0, len(lst), step):
+        q = lst[a:a + step]
+        bra = (q & np.uint64(0xFFFFFF)).astype(np.int64)
+        ket = ((q >> np.uint64(24)) & np.uint64(0xFFFFFF)).astype(np.int64)
+        keep.append(q[sel[bra] | sel[ket]])
+    del lst
+    gsel = np.concatenate(keep)
+    gk = key_set(canonical_keys(gpu_quartet_instances(hfx.unpack_quartets(gsel), pairs)))
+    o = oracle.Oracle(s)
+    o.set_density(D)
+    o.set_q(qb)
+    o.set_pmax(pm)
+    bkey = {tuple(int(v) for v in b): i for i, b in enumerate(plan.blocks)}
+    bra_blocks = [bkey[tuple(int(v) for v in pairs[p, :5])] for p in pick]
+    rows, _ = o.quartets_of_bra_blocks(bra_blocks, gR=3)
+    ok = key_set(canonical_keys(oracle_quartet_instances(rows)))
+    print(f"full-size list: {len(pick)} pairs, {len(gsel)} GPU quartets, {len(ok)} oracle orbits")
+    assert len(gk) == len(gsel)
+    assert gk == ok, (len(gk - ok), len(ok - gk))
+
+
 def test_full_size_sampled_parity():
     """The 64-atom periodic diamond workload of the benchmark at full size:
-    K from a seeded sample of quartets (drawn from the plain loop, one
-    member of each orbit in device orientation) on the GPU against the
-    oracle's plain terms of every member of the same orbits."""
+    K from a seeded, class-stratified sample of quartets (eight orbits of
+    each of the 21 classes drawn from the plain loop, one member of each
+    orbit in device orientation) on the GPU against the oracle's plain terms
+    of every member of the same orbits."""
     from tests.helpers import canonical_keys, gpu_rows, oracle_quartet_instances, orbit_members, to_gpu_quartets
     s = systems.config2_diamond()
     plan = hfx.Plan(s)
     o = oracle.Oracle(s)
     D = _density(s, plan.blocks)
     o.set_density(D)
-    rows = o.sample_quartets(240, seed=11)
-    keys = canonical_keys(oracle_quartet_instances(rows))
-    _, first = np.unique(keys, axis=0, return_index=True)
-    rows = rows[np.sort(first)]
+    # at least 8 distinct orbits of every one of the 21 classes, drawn
+    # uniformly from the plain loop (the rarest class, (dd|dd), is 0.2% of it)
+    ls = s.shell_l
+    chosen, seen = [], set()
+    per = np.zeros(21, dtype=int)
+    for seed in range(11, 31):
+        pool = o.sample_quartets(20000, seed=seed)
+        keys = canonical_keys(oracle_quartet_instances(pool))
+        for row, k in zip(pool, map(tuple, keys.tolist())):
+            r = _region(ls, row[0], row[1], row[5], row[6])
+            if per[r] < 8 and k not in seen:
+                seen.add(k)
+                per[r] += 1
+                chosen.append(row)
+        if per.min() >= 8:
+            break
+    assert per.min() >= 8, per
+    rows = np.array(chosen, dtype=np.int32)
     pairs = plan.export(2)
     q = to_gpu_quartets(rows, pairs, pairs[:, 5])
     # the device representatives are members of the same orbits

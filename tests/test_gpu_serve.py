@@ -1,10 +1,12 @@
 """GPU: the continuous-batching server.  A request's K is the same alone and
 in a mix of requests that arrive while it runs (within 1e-12 relative: only
-the order of the floating-point atomic additions differs), and equals a
-direct build with its last density."""
+the order of the floating-point atomic additions differs), equals a direct
+build with its last density, and equals the oracle's K of that density
+(1e-10 in FP64, 1e-7 for the mixed-precision request)."""
 import numpy as np
 import pytest
 
+import oracle
 import systems
 
 torch = pytest.importorskip("torch")
@@ -44,11 +46,19 @@ def test_alone_equals_in_mix_and_direct_build():
     for r, res in zip(reqs, mix.results):
         plan = hfx.Plan(r.system)
         vals = systems.perturb_density(r.system, plan.blocks.astype(np.int64), r.n_iter - 1)
-        D = torch.from_numpy(np.concatenate([v.ravel() for v in vals])).cuda()
+        Dh = np.concatenate([v.ravel() for v in vals])
+        D = torch.from_numpy(Dh).cuda()
         K = torch.zeros_like(D)
         plan.build_K(D, K, flags=hfx.HFX_SYNC)
         ref = K.cpu().numpy()
         assert np.max(np.abs(res.result - ref)) <= 1e-12 * max(1.0, np.max(np.abs(ref))), r.rid
+        o = oracle.Oracle(r.system)
+        o.set_density(Dh)
+        Ko, _ = o.build_K()
+        tol = 1e-10 if r.system.precision == "fp64" else 1e-7
+        err = np.max(np.abs(res.result - Ko))
+        print(f"request {r.rid} ({r.system.name}, {r.system.precision}): max|dK| vs oracle {err:.3e}")
+        assert err <= tol, r.rid
     s = mix.summary()
     assert s["builds"] == sum(r.n_iter for r in reqs)
     assert 0 < s["latency_ms_p50"] <= s["latency_ms_p99"]
@@ -59,6 +69,16 @@ def test_admission_under_a_tight_limit():
     ex = HipExecutor()
     need = [ex.footprint(r) for r in reqs]
     limit = max(need) + min(need) - 1          # never all three at once
+    torch.cuda.synchronize()
+    torch.cuda.empty_cache()
+    base = ex.device_bytes_in_use()
     st = Server(ex, limit).run(reqs)
     assert st.peak_reserved_bytes <= limit
     assert len(st.results) == 3
+    # the device agrees with the accounting: the memory the admitted
+    # requests really hold (plans, batches, lists, densities and K) stays
+    # within the limit, up to the allocators' page rounding of each of a
+    # plan's few dozen allocations
+    used = ex.peak_device_bytes - base
+    print(f"admission: limit {limit} B, accounted peak {st.peak_reserved_bytes} B, device peak {used} B")
+    assert used <= limit + 2 * (4 << 20)
