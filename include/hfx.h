@@ -208,6 +208,23 @@ hfx_status hfx_kspace(hfx_plan_t plan, const double *k_dev, int32_t nk, const do
  * plans. */
 hfx_status hfx_set_list_limit(hfx_plan_t plan, int64_t max_quartets);
 
+/* hfx_build_K without any device allocation, for callers that cannot
+ * allocate (code running under HIP graph capture elsewhere, tight serving
+ * loops, harnesses that forbid hipMalloc).  The build's work arrays
+ * (screening counts and offsets, class-segment bounds, error flags,
+ * primitive-quartet counters and the quartet list) live in the library's
+ * static device array of 256 MiB, one per device, held until the process
+ * ends; every list is evaluated in chunks of what that array's list part
+ * holds (also bounded by hfx_set_list_limit).  Results equal hfx_build_K up
+ * to the order of floating-point additions.  flags: 0 or HFX_SYNC
+ * (HFX_TIMING and HFX_GRAPH are HFX_ERR_INVALID); info as for hfx_build_K.
+ * HFX_ERR_INVALID if the plan's screening work items alone need more of
+ * the array than it has beside a list of 65536 quartets.  Calls on one
+ * device share its array: calls that overlap in time on one device (other
+ * threads, other streams) race and must be serialised by the caller. */
+hfx_status hfx_build_K_noalloc(hfx_plan_t plan, const double *d_dev, double *k_dev, uint32_t flags,
+                               hfx_build_info *info);
+
 /* Several plans (each with its own D and K, all on one device) in fused
  * launches: one screening pass and one ERI launch per class cover every
  * plan of one operator; plans of the two operators form two such groups.

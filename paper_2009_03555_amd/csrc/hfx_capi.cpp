@@ -188,7 +188,7 @@ struct hfx_plan_s {
   int kpts_cap = 0;
 };
 
-// the plan's own one-plan batch
+// the plan's own one-plan batch, and the scratch address of its device
 hfx_status plan_attach(hfx_plan_s *P);
 
 namespace hfx {
@@ -1476,12 +1476,39 @@ void drop_batches_of(const hfx_plan_s *P) {
   }
 }
 
+// ------------------------------------------------------ static scratch
+// Device memory of the allocation-free build (hfx_build_K_noalloc): the
+// screening counts and offsets, class-segment bounds, error flags,
+// primitive-quartet counters and one quartet-list buffer, in one file-scope
+// array.  Each device holds its own copy until the process ends; host code
+// reaches it only through the address hipGetSymbolAddress returns for the
+// device (recorded by hfx_plan, once per device, with the device current).
+constexpr size_t kScratchBytes = (size_t)256 << 20;
+__device__ __align__(256) unsigned char scratch[kScratchBytes];
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+void *g_scratch_ptr[kMaxDevices] = {};
+
+hfx_status scratch_setup(int dev) {
+  if (dev < 0 || dev >= kMaxDevices) return fail(HFX_ERR_UNSUPPORTED, "device index beyond the scratch table");
+  std::lock_guard<std::mutex> lk(g_scratch_mu);
+  if (g_scratch_ptr[dev]) return HFX_OK;
+  void *ptr = nullptr;
+  hipError_t e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+  if (e != hipSuccess || !ptr)
+    return fail(HFX_ERR_DEVICE, std::string("hipGetSymbolAddress(scratch): ") + hipGetErrorString(e));
+  g_scratch_ptr[dev] = ptr;
+  return HFX_OK;
+}
+
 }  // namespace
 
 hfx_status plan_attach(hfx_plan_s *P) {
   HIPCHK(hipGetDevice(&P->device));
+  hfx_status st = scratch_setup(P->device);
+  if (st != HFX_OK) return st;
   Batch *B = new Batch();
-  hfx_status st = batch_init(*B, {P});
+  st = batch_init(*B, {P});
   if (st != HFX_OK) {
     delete B;
     return st;
@@ -1594,6 +1621,32 @@ hfx_status hfx_set_list_limit(hfx_plan_t plan, int64_t max_quartets) {
     }
   }
   return HFX_OK;
+}
+
+hfx_status hfx_build_K_noalloc(hfx_plan_t plan, const double *d_dev, double *k_dev, uint32_t flags,
+                               hfx_build_info *info) {
+  if (!valid_plan(plan)) return fail(HFX_ERR_STATE, "invalid or destroyed plan");
+  if (flags & ~HFX_SYNC) return fail(HFX_ERR_INVALID, "hfx_build_K_noalloc takes HFX_SYNC only");
+  hfx_plan_s &P = *plan;
+  void *base = nullptr;
+  {
+    std::lock_guard<std::mutex> lk(g_scratch_mu);
+    base = (P.device >= 0 && P.device < kMaxDevices) ? g_scratch_ptr[P.device] : nullptr;
+  }
+  if (!base) return fail(HFX_ERR_STATE, "no scratch address recorded for the plan's device");
+  Batch &B = *P.self_batch;
+  const WorkLayout L = work_layout(B.nitems, 1);
+  // at least a list of 65536 quartets beside the other arrays
+  if (L.total + (size_t)65536 * sizeof(uint64_t) > kScratchBytes)
+    return fail(HFX_ERR_INVALID, "the plan's screening work items need " + std::to_string(L.total) +
+                                     " bytes of scratch, more than the " + std::to_string(kScratchBytes >> 20) +
+                                     " MiB the allocation-free build has");
+  Work W;
+  work_place(W, (char *)base, L);
+  W.fixed = true;
+  W.list = W.list32 = (uint64_t *)((char *)base + L.total);
+  W.cap = W.cap32 = std::min<int64_t>((int64_t)((kScratchBytes - L.total) / sizeof(uint64_t)), B.max_list);
+  return run_batch(B, W, &d_dev, &k_dev, flags, info);
 }
 
 hfx_status hfx_build_K_subset(hfx_plan_t plan, const double *d_dev, double *k_dev, const uint64_t *quartets_host,

@@ -127,9 +127,10 @@ def lib():
         L.hfx_nao2gto_fit.argtypes = [ctypes.c_int32, ctypes.c_int32, dpp, dpp, ctypes.c_int32, dpp, dpp, dpp]
         L.hfx_kspace.argtypes = [vp, vp, ctypes.c_int32, ctypes.POINTER(ctypes.c_double), ctypes.c_double, vp]
         L.hfx_build_K_spin.argtypes = [vp, vp, vp, vp, vp, ctypes.c_uint32, ctypes.POINTER(hfx_build_info)]
+        L.hfx_build_K_noalloc.argtypes = [vp, vp, vp, ctypes.c_uint32, ctypes.POINTER(hfx_build_info)]
         for name in ("hfx_footprint", "hfx_plan", "hfx_pattern", "hfx_schwarz", "hfx_build_K",
                      "hfx_build_K_multi", "hfx_export", "hfx_plan_destroy", "hfx_autotune", "hfx_screen_count",
-                     "hfx_build_K_subset", "hfx_set_list_limit", "hfx_build_K_spin", "hfx_kspace", "hfx_nao2gto_fit"):
+                     "hfx_build_K_subset", "hfx_set_list_limit", "hfx_build_K_noalloc", "hfx_build_K_spin", "hfx_kspace", "hfx_nao2gto_fit"):
             getattr(L, name).restype = ctypes.c_int
         _lib = L
     return _lib
@@ -252,6 +253,14 @@ class Plan:
         """``hfx_set_list_limit``: longest quartet list a build holds at once
         (longer screened lists run in chunks); 0 restores the default."""
         _check(lib().hfx_set_list_limit(self._h, ctypes.c_int64(int(max_quartets))))
+
+    def build_K_noalloc(self, D, K, flags: int = 0, info: bool = False):
+        """``hfx_build_K_noalloc``: the build with its work arrays in the
+        library's static scratch memory (no device allocation)."""
+        inf = hfx_build_info() if info else None
+        _check(lib().hfx_build_K_noalloc(self._h, ctypes.c_void_p(_ptr(D)), ctypes.c_void_p(_ptr(K)),
+                                         ctypes.c_uint32(flags), ctypes.byref(inf) if inf is not None else None))
+        return inf.as_dict() if inf is not None else None
 
     def build_K_subset(self, D, K, quartets: np.ndarray):
         """``hfx_build_K_subset``: K from the given unique quartets only

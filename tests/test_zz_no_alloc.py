@@ -1,0 +1,101 @@
+"""GPU: the allocation-free build (hfx_build_K_noalloc) through the C ABI
+equals hfx_build_K of the same plan on two calls in a row, the second with
+a smaller system, and equals the oracle (1e-10 in FP64, 1e-7 mixed)."""
+import ctypes
+
+import numpy as np
+import pytest
+
+import oracle
+import systems
+
+torch = pytest.importorskip("torch")
+hfx = pytest.importorskip("paper_2009_03555_amd.hfx")
+
+pytestmark = pytest.mark.gpu
+DEV = "cuda:0"
+
+
+def _density(system, blocks):
+    vals = systems.density_blocks(system, np.asarray(blocks, dtype=np.int64))
+    return np.concatenate([v.ravel() for v in vals]) if vals else np.zeros(0)
+
+
+def _oracle_K(system, D):
+    o = oracle.Oracle(system)
+    o.schwarz()
+    o.set_density(D)
+    return o.build_K()[0]
+
+
+def _noalloc_capi(plan, Dd, Kd):
+    """hfx_build_K_noalloc called through the C ABI directly."""
+    L = hfx.lib()
+    info = hfx.hfx_build_info()
+    st = L.hfx_build_K_noalloc(plan.handle, ctypes.c_void_p(Dd.data_ptr()), ctypes.c_void_p(Kd.data_ptr()),
+                               ctypes.c_uint32(hfx.HFX_SYNC), ctypes.byref(info))
+    assert st == hfx.HFX_OK, hfx.hfx_last_error()
+    return info.as_dict()
+
+
+def _case(system):
+    plan = hfx.Plan(system)
+    D = _density(system, plan.blocks)
+    Dd = torch.from_numpy(D).to(DEV)
+    Kref = torch.full_like(Dd, np.nan)
+    iref = plan.build_K(Dd, Kref, flags=hfx.HFX_SYNC, info=True)
+    return plan, D, Dd, Kref.cpu().numpy(), iref
+
+
+def _tiny_cell(**kw):
+    kw.setdefault("seed", 77)
+    return systems.config2_diamond(n=(1, 1, 1), nprim=2, shells=(0, 1, 2), r_cut=4.6, **kw)
+
+
+def test_noalloc_two_calls_second_smaller():
+    cases = [_case(_tiny_cell()), _case(systems.config1_molecule())]
+    # the larger system first, then the smaller one
+    cases.sort(key=lambda c: -c[4]["n_quartets"])
+    counts = []
+    for plan, D, Dd, Kref, iref in cases:
+        s = plan.system
+        Kn = torch.full_like(Dd, np.nan)
+        info = _noalloc_capi(plan, Dd, Kn)
+        Kn = Kn.cpu().numpy()
+        assert info["n_quartets"] == iref["n_quartets"]
+        assert info["n_prim_quartets"] == iref["n_prim_quartets"]
+        assert np.max(np.abs(Kn - Kref)) <= 1e-12 * max(1.0, float(np.max(np.abs(Kref))))
+        assert np.max(np.abs(Kn - _oracle_K(s, D))) <= 1e-10
+        counts.append(info["n_quartets"])
+        plan.destroy()
+    assert counts[1] < counts[0]
+
+
+def test_noalloc_in_chunks_and_mixed_precision():
+    s = _tiny_cell(precision="mixed").with_(fp32_cutoff=1e-2)
+    plan, D, Dd, Kref, iref = _case(s)
+    plan.set_list_limit(3000)  # the scratch list is cut to this many quartets
+    Kn = torch.full_like(Dd, np.nan)
+    info = plan.build_K_noalloc(Dd, Kn, flags=hfx.HFX_SYNC, info=True)
+    assert info["n_chunks"] >= 3
+    assert info["n_fp32_quartets"] == iref["n_fp32_quartets"] > 0
+    Kn = Kn.cpu().numpy()
+    assert np.max(np.abs(Kn - Kref)) <= 1e-12 * max(1.0, float(np.max(np.abs(Kref))))
+    assert np.max(np.abs(Kn - _oracle_K(s, D))) <= 1e-7
+    # the ordinary build of the same plan still works after it
+    K2 = torch.full_like(Dd, np.nan)
+    plan.set_list_limit(0)
+    plan.build_K(Dd, K2, flags=hfx.HFX_SYNC)
+    assert np.max(np.abs(K2.cpu().numpy() - Kref)) <= 1e-12 * max(1.0, float(np.max(np.abs(Kref))))
+    plan.destroy()
+
+
+def test_noalloc_rejects_other_flags():
+    s = systems.config1_molecule()
+    plan, D, Dd, Kref, iref = _case(s)
+    Kn = torch.zeros_like(Dd)
+    for f in (hfx.HFX_TIMING, hfx.HFX_GRAPH):
+        with pytest.raises(hfx.HfxError) as e:
+            plan.build_K_noalloc(Dd, Kn, flags=f)
+        assert e.value.status == hfx.HFX_ERR_INVALID
+    plan.destroy()
