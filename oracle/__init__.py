@@ -67,6 +67,7 @@ def lib():
         L.oracle_set_density.argtypes = [ctypes.c_void_p, dp, dp]
         L.oracle_set_pmax.argtypes = [ctypes.c_void_p, dp]
         L.oracle_set_q.argtypes = [ctypes.c_void_p, dp]
+        L.oracle_schwarz_rows.argtypes = [ctypes.c_void_p, ctypes.c_int64, i32p, dp]
         L.oracle_quartets_bra.restype = ctypes.c_int64
         L.oracle_quartets_bra.argtypes = [ctypes.c_void_p, ctypes.c_int, ctypes.c_int64, i64p, ctypes.c_int64,
                                           i32p, dp]
@@ -258,6 +259,16 @@ class Oracle:
         self.Pmax = np.zeros(len(self.blocks))
         lib().oracle_set_density(self.h, _p(d), _p(self.Pmax))
         return self.Pmax
+
+    def schwarz_rows(self, rows) -> np.ndarray:
+        """Schwarz factors of the blocks of the given shell rows only (what
+        K blocks of those rows need); other blocks are zero until computed."""
+        if self.Q is None:
+            self.Q = np.zeros(len(self.blocks))
+            lib().oracle_set_q(self.h, _p(self.Q))
+        r = np.ascontiguousarray(sorted(set(int(x) for x in rows)), dtype=np.int32)
+        lib().oracle_schwarz_rows(self.h, len(r), _p(r, ctypes.c_int32), _p(self.Q))
+        return self.Q
 
     def set_q(self, q: np.ndarray) -> None:
         """Replace the Schwarz factors (one per block) used by the screening."""

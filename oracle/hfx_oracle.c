@@ -530,6 +530,36 @@ void oracle_schwarz(void *h, double *q_out) {
   if (q_out) memcpy(q_out, s->Q, sizeof(double) * s->nblk);
 }
 
+/* Schwarz factors of the blocks of the given rows only (a K block (I, K, G)
+ * needs the pairs of rows I and K), each from its own orientation; the
+ * other blocks keep their value.  Same definition as oracle_schwarz. */
+void oracle_schwarz_rows(void *h, int64_t nrows, const int32_t *rows, double *q_out) {
+  osys *s = (osys *)h;
+  for (int64_t k = 0; k < nrows; ++k) {
+    const int I = rows[k];
+#pragma omp parallel for schedule(dynamic, 4)
+    for (int64_t b = s->row_start[I]; b < s->row_start[I + 1]; ++b) {
+      const int32_t *x = s->blk + 5 * b;
+      int z[3] = {0, 0, 0}, n[3] = {x[2], x[3], x[4]};
+      oshell A, B;
+      make_shell(s, x[0], z, &A);
+      make_shell(s, x[1], n, &B);
+      int na = ncart(A.l), nb = ncart(B.l);
+      double *e = (double *)malloc(sizeof(double) * na * nb * na * nb);
+      oracle_eri_quartet(&A, &B, &A, &B, s->op, s->omega, e);
+      double m = 0.0;
+      for (int i = 0; i < na; ++i)
+        for (int j = 0; j < nb; ++j) {
+          double v = fabs(e[((i * nb + j) * na + i) * nb + j]);
+          if (v > m) m = v;
+        }
+      free(e);
+      s->Q[b] = sqrt(m);
+    }
+  }
+  if (q_out) memcpy(q_out, s->Q, sizeof(double) * s->nblk);
+}
+
 /* D in the boundary basis (pattern order) -> Cartesian blocks and P_max.
  * D_cart = T_I^T D T_J; P_max of the canonical block, copied to its partner. */
 void oracle_set_density(void *h, const double *d, double *pmax_out) {

@@ -1,0 +1,153 @@
+"""Full-size run of the mixed-precision cluster workload (256 atoms at 0.1
+atoms/bohr^3, heavy s,s,p,p,d and light s,s,p atoms, 4 primitives, bare
+Coulomb, FP32 allowed below Q_IJ Q_KL = 1e-6) on the GPU, with the mixed
+build's error against the FP64 oracle reported per K block.
+
+Not collected by pytest (minutes of GPU time, tens of minutes of host time
+for the oracle's blocks, whose rows keep nearly every candidate quartet on
+this diffuse basis).  Run as
+``python tests/fullsize_config3.py --gpu-out F.npz`` on the GPU (builds,
+counts, the sampled blocks' K saved to F.npz and a JSON line), then
+``python tests/fullsize_config3.py --check F.npz`` on any host (the oracle on
+the same seeded blocks, per-block errors, a JSON line); without either
+option both run in one process.
+Steps: screened counts (FP64 and FP32 lists); one FP64 and one mixed build,
+timed, with the lists evaluated in chunks of at most the list limit; the
+oracle's K on a seeded sample of K blocks (half uniform over the pattern,
+half among blocks of shells within 5 bohr, where K is large), with the
+Schwarz factors of only the rows those blocks need; per sampled block the
+largest |dK| of the mixed and of the FP64 build against the oracle; the
+mixed build against the FP64 build on every element.  Prints one JSON
+object (and writes it to --out)."""
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+import numpy as np  # noqa: E402
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--blocks", type=int, default=32)
+    ap.add_argument("--list-limit", type=int, default=0, help="quartets per list chunk (0: the library default)")
+    ap.add_argument("--atoms", type=int, default=256)
+    ap.add_argument("--out", default="")
+    ap.add_argument("--gpu-out", default="", help="GPU part only: save the sampled blocks' K here (.npz)")
+    ap.add_argument("--check", default="", help="host part only: oracle against the K saved by --gpu-out")
+    args = ap.parse_args()
+
+    def log(msg):
+        print(f"# {msg}", file=sys.stderr, flush=True)
+
+    import systems
+    smx = systems.config3_cluster(n_atoms=args.atoms)
+    s64 = smx.with_(precision="fp64")
+    if args.check:
+        return check(args, s64, log)
+    import torch
+    from paper_2009_03555_amd import hfx
+    out = {"workload": smx.name, "n_atoms": smx.n_atoms, "n_shells": smx.n_shells,
+           "n_basis": smx.n_functions(), "fp32_cutoff": smx.fp32_cutoff, "tau": smx.tau}
+    p64 = hfx.Plan(s64)
+    pmx = hfx.Plan(smx)
+    if args.list_limit:
+        p64.set_list_limit(args.list_limit)
+        pmx.set_list_limit(args.list_limit)
+    log(f"{smx.name}: {smx.n_shells} shells, {p64.n_blocks} blocks, nnz {p64.nnz}")
+    D = np.concatenate([v.ravel() for v in systems.density_blocks(s64, p64.blocks.astype(np.int64))])
+    Dd = torch.from_numpy(D).cuda()
+    n64, _ = p64.screen_count(Dd)
+    m64, m32 = pmx.screen_count(Dd)
+    out.update(quartets=n64, mixed_fp64_list=m64, mixed_fp32_list=m32, fp32_fraction=m32 / max(1, m64 + m32))
+    log(f"screened: {n64} quartets; mixed lists {m64} FP64 + {m32} FP32 ({out['fp32_fraction']:.3f})")
+    K64 = torch.zeros_like(Dd)
+    Kmx = torch.zeros_like(Dd)
+    res = {}
+    for name, plan, K in (("fp64", p64, K64), ("mixed", pmx, Kmx)):
+        torch.cuda.synchronize()
+        t = time.perf_counter()
+        info = plan.build_K(Dd, K, flags=hfx.HFX_TIMING, info=True)
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t
+        res[name] = {"build_s": dt, "quartets": info["n_quartets"], "quartets_per_s": info["n_quartets"] / dt,
+                     "fp32_quartets": info["n_fp32_quartets"], "prim_quartets": info["n_prim_quartets"],
+                     "chunks": info["n_chunks"], "eri_tflops_algorithmic": info["flops"] / dt / 1e12}
+        log(f"{name} build: {dt:.1f} s, {info['n_quartets']} quartets, {info['n_chunks']} chunks, "
+            f"{info['n_fp32_quartets']} FP32")
+    out["builds"] = res
+    out["speedup_mixed_vs_fp64"] = res["fp64"]["build_s"] / res["mixed"]["build_s"]
+    k64, kmx = K64.cpu().numpy(), Kmx.cpu().numpy()
+    out["max_abs_dK_mixed_vs_fp64_all"] = float(np.max(np.abs(kmx - k64)))
+    out["max_abs_K"] = float(np.max(np.abs(k64)))
+    log(f"mixed vs FP64 on every element: {out['max_abs_dK_mixed_vs_fp64_all']:.3e}")
+    pick = sample_blocks(s64, p64.blocks, args.blocks)
+    off = p64.offsets
+    idx = np.concatenate([np.arange(off[b], off[b + 1]) for b in pick])
+    out["sampled_blocks"] = len(pick)
+    if args.gpu_out:
+        np.savez(args.gpu_out, pick=pick, k64=k64[idx], kmx=kmx[idx], summary=json.dumps(out))
+        print(json.dumps(out), flush=True)
+        return 0
+    np.savez("/tmp/_config3_k.npz", pick=pick, k64=k64[idx], kmx=kmx[idx], summary=json.dumps(out))
+    args.check = "/tmp/_config3_k.npz"
+    return check(args, s64, log)
+
+
+def sample_blocks(system, blocks, n):
+    """Seeded K blocks: half uniform over the pattern, half among blocks of
+    shells within 5 bohr (where K is large)."""
+    blocks = np.asarray(blocks, dtype=np.int64)
+    rng = np.random.default_rng(3003)
+    xyz = np.asarray(system.atom_xyz)[np.asarray(system.shell_atom)]
+    dist = np.linalg.norm(xyz[blocks[:, 0]] - xyz[blocks[:, 1]], axis=1)
+    near = np.flatnonzero(dist < 5.0)
+    half = n // 2
+    return np.unique(np.concatenate([rng.choice(len(blocks), n - half, replace=False),
+                                     rng.choice(near, half, replace=False)]))
+
+
+def check(args, s64, log):
+    import oracle
+    z = np.load(args.check)
+    out = json.loads(str(z["summary"]))
+    o = oracle.Oracle(s64)
+    blocks = o.blocks.astype(np.int64)
+    pick = sample_blocks(s64, blocks, args.blocks)
+    assert np.array_equal(pick, z["pick"]), "the saved K is of other blocks"
+    t = time.perf_counter()
+    o.schwarz_rows(np.concatenate([blocks[pick, 0], blocks[pick, 1]]))
+    o.set_density(o.density_from_system())
+    Kref, nterms = o.build_K(blocks=pick)
+    dt = time.perf_counter() - t
+    log(f"oracle: {len(pick)} K blocks, {nterms} ordered quartets, {dt:.1f} s")
+    per, a = [], 0
+    for b in pick:
+        n = int(o.offsets[b + 1] - o.offsets[b])
+        ref = Kref[o.offsets[b]:o.offsets[b + 1]]
+        per.append({"block": [int(v) for v in blocks[b]], "max_abs_K": float(np.max(np.abs(ref))),
+                    "max_abs_dK_mixed": float(np.max(np.abs(z["kmx"][a:a + n] - ref))),
+                    "max_abs_dK_fp64": float(np.max(np.abs(z["k64"][a:a + n] - ref)))})
+        a += n
+    out["oracle_blocks"] = per
+    out["oracle_ordered_quartets"] = int(nterms)
+    out["oracle_s"] = dt
+    out["max_abs_dK_mixed_vs_oracle"] = max(p["max_abs_dK_mixed"] for p in per)
+    out["max_abs_dK_fp64_vs_oracle"] = max(p["max_abs_dK_fp64"] for p in per)
+    log(f"per-block max|dK| vs oracle: mixed {out['max_abs_dK_mixed_vs_oracle']:.3e}, "
+        f"FP64 {out['max_abs_dK_fp64_vs_oracle']:.3e}")
+    line = json.dumps(out)
+    print(line, flush=True)
+    if args.out:
+        with open(args.out, "w") as f:
+            f.write(line + "\n")
+    return 0 if (out["max_abs_dK_mixed_vs_oracle"] <= 1e-7 and out["max_abs_dK_fp64_vs_oracle"] <= 1e-10) else 1
+
+
+if __name__ == "__main__":
+    sys.exit(main())

@@ -281,3 +281,19 @@ def test_pmax_of_one_element_is_its_magnitude_on_its_two_blocks(periodic):
         expect = np.zeros(len(blocks))
         expect[i] = expect[j] = abs(v)
         assert np.array_equal(pmax, expect), (trial, i, j)
+
+
+def test_schwarz_of_chosen_rows_equals_the_full_table():
+    # the row-restricted Schwarz step (for K blocks of chosen rows) agrees
+    # with the pinned full table on those rows' blocks
+    s = _tiny_system(True, "erfc")
+    full = oracle.Oracle(s)
+    Q = full.schwarz()
+    part = oracle.Oracle(s)
+    rows = [1, 4]
+    q = part.schwarz_rows(rows)
+    for i, b in enumerate(part.blocks):
+        if int(b[0]) in rows:
+            assert q[i] == pytest.approx(Q[i], rel=1e-13)
+        else:
+            assert q[i] == 0.0
