@@ -158,6 +158,18 @@ hfx_status hfx_schwarz(hfx_plan_t plan, double *q_host, int64_t *n_pairs);
 hfx_status hfx_build_K(hfx_plan_t plan, const double *d_dev, double *k_dev, uint32_t flags,
                        hfx_build_info *info);
 
+/* Progress of chunked builds: fn(user, list, chunk, quartets_done,
+ * quartets_total) is called on the calling thread after the device has
+ * finished each chunk of a chunked list (list 0: the FP64 list, 1: the FP32
+ * list of mixed precision; chunk: chunks finished so far in this build;
+ * quartets of this list up to the end of the chunk, and in the whole list).
+ * Setting it makes chunked builds wait for each chunk before screening the
+ * next.  fn = NULL turns the reports off.  Fused multi-plan builds report to
+ * the first plan's function. */
+typedef void (*hfx_progress_fn)(void *user, int32_t list, int64_t chunk, int64_t quartets_done,
+                                int64_t quartets_total);
+hfx_status hfx_set_progress(hfx_plan_t plan, hfx_progress_fn fn, void *user);
+
 /* Collinear spin: the exchange matrix of each spin density,
  * K^s_{mu nu} = sum_{lambda sigma} (mu lambda|nu sigma) D^s_{lambda sigma},
  * s = alpha, beta - Eq. H-HFX applied per spin, the spin-polarised form of

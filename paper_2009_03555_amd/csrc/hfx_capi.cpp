@@ -186,6 +186,9 @@ struct hfx_plan_s {
   int64_t nbf = 0;
   double *d_kpts = nullptr;
   int kpts_cap = 0;
+  // progress report of chunked builds (hfx_set_progress)
+  hfx_progress_fn progress = nullptr;
+  void *progress_user = nullptr;
 };
 
 // the plan's own one-plan batch, and the scratch address of its device
@@ -1117,6 +1120,13 @@ hfx_status run_chunks(Batch &B, Work &W, int mode, bool f32, uint64_t *list, int
       }
       launch_classes(B, W, f32, list, d_seg, hs.data());
       ++B.n_chunks;
+      // a plan that asked for progress reports hears of each chunk once
+      // the device has finished it
+      hfx_plan_s &P0 = *B.plans[0];
+      if (P0.progress) {
+        HIPCHK(hipStreamSynchronize(B.stream));
+        P0.progress(P0.progress_user, f32 ? 1 : 0, B.n_chunks, end, off[nit]);
+      }
     }
     i0 = i1;
   }
@@ -1591,6 +1601,13 @@ hfx_status hfx_kspace(hfx_plan_t plan, const double *k_dev, int32_t nk, const do
   // the k-points were copied from pageable host memory: wait so that the
   // caller may reuse them at once
   HIPCHK(hipStreamSynchronize(P.stream));
+  return HFX_OK;
+}
+
+hfx_status hfx_set_progress(hfx_plan_t plan, hfx_progress_fn fn, void *user) {
+  if (!valid_plan(plan)) return fail(HFX_ERR_STATE, "invalid or destroyed plan");
+  plan->progress = fn;
+  plan->progress_user = user;
   return HFX_OK;
 }
 

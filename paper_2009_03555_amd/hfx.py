@@ -96,6 +96,9 @@ class hfx_tune_report(ctypes.Structure):
         return out
 
 
+PROGRESS_FN = ctypes.CFUNCTYPE(None, ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64, ctypes.c_int64,
+                               ctypes.c_int64)
+
 _lib = None
 
 
@@ -123,6 +126,7 @@ def lib():
         L.hfx_screen_count.argtypes = [vp, vp, ctypes.POINTER(ctypes.c_int64), ctypes.POINTER(ctypes.c_int64)]
         L.hfx_build_K_subset.argtypes = [vp, vp, vp, ctypes.POINTER(ctypes.c_uint64), ctypes.c_int64]
         L.hfx_set_list_limit.argtypes = [vp, ctypes.c_int64]
+        L.hfx_set_progress.argtypes = [vp, PROGRESS_FN, vp]
         dpp = ctypes.POINTER(ctypes.c_double)
         L.hfx_nao2gto_fit.argtypes = [ctypes.c_int32, ctypes.c_int32, dpp, dpp, ctypes.c_int32, dpp, dpp, dpp]
         L.hfx_kspace.argtypes = [vp, vp, ctypes.c_int32, ctypes.POINTER(ctypes.c_double), ctypes.c_double, vp]
@@ -130,7 +134,7 @@ def lib():
         L.hfx_build_K_noalloc.argtypes = [vp, vp, vp, ctypes.c_uint32, ctypes.POINTER(hfx_build_info)]
         for name in ("hfx_footprint", "hfx_plan", "hfx_pattern", "hfx_schwarz", "hfx_build_K",
                      "hfx_build_K_multi", "hfx_export", "hfx_plan_destroy", "hfx_autotune", "hfx_screen_count",
-                     "hfx_build_K_subset", "hfx_set_list_limit", "hfx_build_K_noalloc", "hfx_build_K_spin", "hfx_kspace", "hfx_nao2gto_fit"):
+                     "hfx_build_K_subset", "hfx_set_list_limit", "hfx_build_K_noalloc", "hfx_build_K_spin", "hfx_kspace", "hfx_nao2gto_fit", "hfx_set_progress"):
             getattr(L, name).restype = ctypes.c_int
         _lib = L
     return _lib
@@ -248,6 +252,16 @@ class Plan:
         _check(lib().hfx_kspace(self._h, ctypes.c_void_p(_ptr(K)), len(k),
                                 k.ctypes.data_as(ctypes.POINTER(ctypes.c_double)), ctypes.c_double(alpha),
                                 ctypes.c_void_p(H.data_ptr())))
+
+    def set_progress(self, fn):
+        """``hfx_set_progress``: fn(list, chunk, quartets_done, quartets_total)
+        after each finished chunk of a chunked build (None: off)."""
+        if fn is None:
+            self._progress = None
+            _check(lib().hfx_set_progress(self._h, PROGRESS_FN(), None))
+            return
+        self._progress = PROGRESS_FN(lambda user, lst, chunk, done, total: fn(lst, chunk, done, total))
+        _check(lib().hfx_set_progress(self._h, self._progress, None))
 
     def set_list_limit(self, max_quartets: int):
         """``hfx_set_list_limit``: longest quartet list a build holds at once

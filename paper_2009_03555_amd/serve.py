@@ -64,6 +64,7 @@ class ServeStats:
     builds: int
     max_concurrent: int
     peak_reserved_bytes: int
+    unfinished: List[int] = dataclasses.field(default_factory=list)  # requests cut off by stop_after_s
 
     def latency_percentile(self, q: float) -> float:
         return float(np.percentile([r.latency_s for r in self.results], q)) if self.results else 0.0
@@ -77,24 +78,38 @@ class ServeStats:
                 "wall_s": self.wall_s, "builds_per_s": self.builds_per_s,
                 "latency_ms_p50": self.latency_percentile(50) * 1e3,
                 "latency_ms_p99": self.latency_percentile(99) * 1e3,
-                "max_concurrent": self.max_concurrent, "peak_reserved_bytes": self.peak_reserved_bytes}
+                "max_concurrent": self.max_concurrent, "peak_reserved_bytes": self.peak_reserved_bytes,
+                "unfinished_requests": len(self.unfinished)}
 
 
 class Server:
     """Iteration-level continuous batching under an HBM budget."""
 
     def __init__(self, executor, hbm_limit_bytes: int, max_batch: int = 64, step_budget: float = 0.0,
-                 clock: Optional[Callable[[], float]] = None, sleep: Optional[Callable[[float], None]] = None):
-        """step_budget > 0: a step runs the admitted requests in admission
-        order only while their summed ``executor.cost`` stays within the
-        budget (at least one); the others keep their device state and wait
-        for the next step.  0: every admitted request runs every step."""
+                 clock: Optional[Callable[[], float]] = None, sleep: Optional[Callable[[float], None]] = None,
+                 policy: str = "fifo", stop_after_s: float = 0.0):
+        """step_budget > 0: a step runs admitted requests only while their
+        summed ``executor.cost`` stays within the budget (at least one); the
+        others keep their device state and wait for the next step.  0: every
+        admitted request runs every step.  policy: the order in which a
+        budgeted step takes requests - "fifo" (admission order), "las"
+        (least attained service: the request that has had the least work so
+        far first) or "srpt" (shortest remaining work first: cost of one
+        build times the iterations left); the first in that order always
+        runs, the rest if they fit, so that under "las" and "srpt" short
+        requests are not held behind a long one.  stop_after_s > 0: no step
+        starts after this time; unfinished requests are reported, not
+        retired results."""
+        if policy not in ("fifo", "las", "srpt"):
+            raise ValueError("policy must be 'fifo', 'las' or 'srpt'")
         self.ex = executor
         self.limit = int(hbm_limit_bytes)
         self.max_batch = int(max_batch)
         self.budget = float(step_budget)
         self.clock = clock or time.perf_counter
         self.sleep = sleep or time.sleep
+        self.policy = policy
+        self.stop_after = float(stop_after_s)
 
     def run(self, requests: Sequence[ServeRequest]) -> ServeStats:
         queue = sorted(requests, key=lambda r: (r.arrival_s, r.rid))
@@ -102,7 +117,7 @@ class Server:
             if self.ex.static_footprint(r) > self.limit:
                 raise ValueError(f"request {r.rid} needs more device memory than the limit")
         t0 = self.clock()
-        active = []          # [request, state, reserved bytes, iterations done, admitted time, steps]
+        active = []          # [request, state, reserved bytes, iterations done, admitted time, steps, work done]
         results: List[ServeResult] = []
         reserved = 0
         peak = 0
@@ -110,8 +125,12 @@ class Server:
         builds = 0
         max_conc = 0
         qi = 0
+        stopped = False
         while qi < len(queue) or active:
             now = self.clock() - t0
+            if self.stop_after > 0 and now >= self.stop_after:
+                stopped = True
+                break
             # admit arrived requests in FIFO order while they fit
             while (qi < len(queue) and queue[qi].arrival_s <= now and len(active) < self.max_batch):
                 need = self.ex.footprint(queue[qi])
@@ -120,7 +139,7 @@ class Server:
                 st = self.ex.admit(queue[qi])
                 reserved += need
                 peak = max(peak, reserved)
-                active.append([queue[qi], st, need, 0, now, []])
+                active.append([queue[qi], st, need, 0, now, [], 0.0])
                 qi += 1
             if not active:
                 # idle until the next arrival
@@ -128,11 +147,19 @@ class Server:
                 continue
             run = active
             if self.budget > 0:
+                if self.policy == "fifo":
+                    order = active
+                elif self.policy == "las":
+                    order = sorted(active, key=lambda a: a[6])
+                else:
+                    order = sorted(active, key=lambda a: self.ex.cost(a[1]) * (a[0].n_iter - a[3]))
                 run, used = [], 0.0
-                for a in active:
+                for a in order:
                     c = self.ex.cost(a[1])
                     if run and used + c > self.budget:
-                        break
+                        if self.policy == "fifo":
+                            break
+                        continue
                     run.append(a)
                     used += c
             max_conc = max(max_conc, len(run))
@@ -148,6 +175,7 @@ class Server:
                     continue
                 a[3] += 1
                 a[5].append(n_steps - 1)
+                a[6] += self.ex.cost(a[1]) if self.budget > 0 else 1.0
                 if a[3] >= a[0].n_iter:
                     res = self.ex.retire(a[1])
                     reserved -= a[2]
@@ -157,7 +185,10 @@ class Server:
             active = still
         wall = self.clock() - t0
         results.sort(key=lambda r: r.rid)
-        return ServeStats(results, wall, n_steps, builds, max_conc, peak)
+        unfinished = [a[0].rid for a in active] + [r.rid for r in queue[qi:]] if stopped else []
+        for a in active:
+            self.ex.retire(a[1])
+        return ServeStats(results, wall, n_steps, builds, max_conc, peak, unfinished)
 
 
 class HipExecutor:
@@ -189,6 +220,7 @@ class HipExecutor:
         self._fp = {}
         self._nq = {}
         self.peak_device_bytes = 0
+        self.quartets_done = 0  # screened quartets (of each request's first density) of the builds run
 
     def _densities(self, req: ServeRequest, blocks, iterations):
         import systems
@@ -246,6 +278,7 @@ class HipExecutor:
         self.peak_device_bytes = max(self.peak_device_bytes, self.device_bytes_in_use())
         for s in states:
             s["it"] += 1
+            self.quartets_done += s["quartets"]
 
     def retire(self, state):
         out = state["buf"][-1].cpu().numpy() if self.keep else None

@@ -268,14 +268,19 @@ def config5_requests(seed: int = 1004, n_requests: int = 200, rate_per_s: float 
                      cluster_range=(10, 500), cell_atoms=(8, 16, 32, 64, 128),
                      n_iter: int = 10, precision: str = "mixed",
                      cluster_nprim: int = 4, cell_nprim: int = 6) -> List[Request]:
-    """Seeded prefix of the Poisson request stream (50% clusters, 50% cells)."""
+    """The first n_requests of the seeded Poisson request stream (50%
+    clusters, 50% cells).  Draw order, request by request: the gap to the
+    previous arrival, the kind, the cluster size, the cell size; so the
+    first k requests are the same for every n_requests >= k."""
     rng = np.random.Generator(np.random.PCG64(seed))
-    gaps = rng.exponential(1.0 / rate_per_s, size=n_requests)
-    t = np.cumsum(gaps)
-    kinds = rng.integers(0, 2, size=n_requests)
     lo, hi = cluster_range
-    sizes = np.exp(rng.uniform(math.log(lo), math.log(hi), size=n_requests))
-    cells = rng.integers(0, len(cell_atoms), size=n_requests)
+    gaps, kinds, sizes, cells = [], [], [], []
+    for _ in range(n_requests):
+        gaps.append(rng.exponential(1.0 / rate_per_s))
+        kinds.append(int(rng.integers(0, 2)))
+        sizes.append(float(np.exp(rng.uniform(math.log(lo), math.log(hi)))))
+        cells.append(int(rng.integers(0, len(cell_atoms))))
+    t = np.cumsum(gaps)
     shapes = {8: (1, 1, 1), 16: (2, 1, 1), 32: (2, 2, 1), 64: (2, 2, 2), 128: (4, 2, 2)}
     out = []
     for i in range(n_requests):

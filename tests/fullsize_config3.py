@@ -6,11 +6,13 @@ build's error against the FP64 oracle reported per K block.
 Not collected by pytest (minutes of GPU time, tens of minutes of host time
 for the oracle's blocks, whose rows keep nearly every candidate quartet on
 this diffuse basis).  Run as
-``python tests/fullsize_config3.py --gpu-out F.npz`` on the GPU (builds,
-counts, the sampled blocks' K saved to F.npz and a JSON line), then
-``python tests/fullsize_config3.py --check F.npz`` on any host (the oracle on
-the same seeded blocks, per-block errors, a JSON line); without either
-option both run in one process.
+``python tests/fullsize_config3.py --gpu-out P --forms fp64`` and
+``... --gpu-out P --forms mixed`` on the GPU (counts, the timed build with a
+progress line per list chunk, K saved to P_fp64.npz / P_mixed.npz and a
+JSON line), then ``python tests/fullsize_config3.py --check P`` on any host
+(mixed against FP64 on every element, the oracle on the seeded blocks,
+per-block errors, a JSON line); without --gpu-out or --check everything
+runs in one process.
 Steps: screened counts (FP64 and FP32 lists); one FP64 and one mixed build,
 timed, with the lists evaluated in chunks of at most the list limit; the
 oracle's K on a seeded sample of K blocks (half uniform over the pattern,
@@ -40,6 +42,10 @@ def main():
     ap.add_argument("--out", default="")
     ap.add_argument("--gpu-out", default="", help="GPU part only: save the sampled blocks' K here (.npz)")
     ap.add_argument("--check", default="", help="host part only: oracle against the K saved by --gpu-out")
+    ap.add_argument("--forms", nargs="+", default=["fp64", "mixed"], choices=["fp64", "mixed"],
+                    help="GPU part: which builds to run (both are needed for the check)")
+    ap.add_argument("--stride", type=int, default=1,
+                    help="host part: check every stride-th saved block only (the oracle needs minutes per block)")
     args = ap.parse_args()
 
     def log(msg):
@@ -54,48 +60,44 @@ def main():
     from paper_2009_03555_amd import hfx
     out = {"workload": smx.name, "n_atoms": smx.n_atoms, "n_shells": smx.n_shells,
            "n_basis": smx.n_functions(), "fp32_cutoff": smx.fp32_cutoff, "tau": smx.tau}
-    p64 = hfx.Plan(s64)
-    pmx = hfx.Plan(smx)
-    if args.list_limit:
-        p64.set_list_limit(args.list_limit)
-        pmx.set_list_limit(args.list_limit)
-    log(f"{smx.name}: {smx.n_shells} shells, {p64.n_blocks} blocks, nnz {p64.nnz}")
-    D = np.concatenate([v.ravel() for v in systems.density_blocks(s64, p64.blocks.astype(np.int64))])
-    Dd = torch.from_numpy(D).cuda()
-    n64, _ = p64.screen_count(Dd)
-    m64, m32 = pmx.screen_count(Dd)
-    out.update(quartets=n64, mixed_fp64_list=m64, mixed_fp32_list=m32, fp32_fraction=m32 / max(1, m64 + m32))
-    log(f"screened: {n64} quartets; mixed lists {m64} FP64 + {m32} FP32 ({out['fp32_fraction']:.3f})")
-    K64 = torch.zeros_like(Dd)
-    Kmx = torch.zeros_like(Dd)
-    res = {}
-    for name, plan, K in (("fp64", p64, K64), ("mixed", pmx, Kmx)):
+    forms = {"fp64": s64, "mixed": smx}
+    K = {}
+    for name in args.forms:
+        plan = hfx.Plan(forms[name])
+        if args.list_limit:
+            plan.set_list_limit(args.list_limit)
+        if "n_blocks" not in out:
+            log(f"{smx.name}: {smx.n_shells} shells, {plan.n_blocks} blocks, nnz {plan.nnz}")
+            D = np.concatenate([v.ravel() for v in systems.density_blocks(s64, plan.blocks.astype(np.int64))])
+            Dd = torch.from_numpy(D).cuda()
+            out.update(n_blocks=plan.n_blocks, nnz=plan.nnz)
+        n64, n32 = plan.screen_count(Dd)
+        log(f"{name}: screened {n64} + {n32} quartets (FP64 + FP32 lists)")
+        plan.set_progress(lambda lst, chunk, done, total, name=name:
+                          log(f"{name} list {lst}: chunk {chunk} done, {done}/{total} quartets"))
+        Kd = torch.zeros_like(Dd)
         torch.cuda.synchronize()
         t = time.perf_counter()
-        info = plan.build_K(Dd, K, flags=hfx.HFX_TIMING, info=True)
+        info = plan.build_K(Dd, Kd, flags=hfx.HFX_TIMING, info=True)
         torch.cuda.synchronize()
         dt = time.perf_counter() - t
-        res[name] = {"build_s": dt, "quartets": info["n_quartets"], "quartets_per_s": info["n_quartets"] / dt,
-                     "fp32_quartets": info["n_fp32_quartets"], "prim_quartets": info["n_prim_quartets"],
-                     "chunks": info["n_chunks"], "eri_tflops_algorithmic": info["flops"] / dt / 1e12}
+        out[name] = {"build_s": dt, "quartets": info["n_quartets"], "quartets_per_s": info["n_quartets"] / dt,
+                     "fp32_quartets": info["n_fp32_quartets"], "fp32_fraction": info["n_fp32_quartets"] / max(
+                         1, info["n_quartets"]), "prim_quartets": info["n_prim_quartets"],
+                     "chunks": info["n_chunks"], "flops_algorithmic": info["flops"],
+                     "eri_tflops_algorithmic": info["flops"] / dt / 1e12}
         log(f"{name} build: {dt:.1f} s, {info['n_quartets']} quartets, {info['n_chunks']} chunks, "
             f"{info['n_fp32_quartets']} FP32")
-    out["builds"] = res
-    out["speedup_mixed_vs_fp64"] = res["fp64"]["build_s"] / res["mixed"]["build_s"]
-    k64, kmx = K64.cpu().numpy(), Kmx.cpu().numpy()
-    out["max_abs_dK_mixed_vs_fp64_all"] = float(np.max(np.abs(kmx - k64)))
-    out["max_abs_K"] = float(np.max(np.abs(k64)))
-    log(f"mixed vs FP64 on every element: {out['max_abs_dK_mixed_vs_fp64_all']:.3e}")
-    pick = sample_blocks(s64, p64.blocks, args.blocks)
-    off = p64.offsets
-    idx = np.concatenate([np.arange(off[b], off[b + 1]) for b in pick])
-    out["sampled_blocks"] = len(pick)
+        K[name] = Kd.cpu().numpy()
+        plan.destroy()
     if args.gpu_out:
-        np.savez(args.gpu_out, pick=pick, k64=k64[idx], kmx=kmx[idx], summary=json.dumps(out))
+        for name, k in K.items():
+            np.savez(f"{args.gpu_out}_{name}.npz", k=k, summary=json.dumps(out))
         print(json.dumps(out), flush=True)
         return 0
-    np.savez("/tmp/_config3_k.npz", pick=pick, k64=k64[idx], kmx=kmx[idx], summary=json.dumps(out))
-    args.check = "/tmp/_config3_k.npz"
+    for name, k in K.items():
+        np.savez(f"/tmp/_config3_{name}.npz", k=k, summary=json.dumps(out))
+    args.check = "/tmp/_config3"
     return check(args, s64, log)
 
 
@@ -114,26 +116,33 @@ def sample_blocks(system, blocks, n):
 
 def check(args, s64, log):
     import oracle
-    z = np.load(args.check)
-    out = json.loads(str(z["summary"]))
+    zs = {name: np.load(f"{args.check}_{name}.npz") for name in ("fp64", "mixed")}
+    out = {}
+    for name, z in zs.items():
+        out.update(json.loads(str(z["summary"])))
+    k64, kmx = zs["fp64"]["k"], zs["mixed"]["k"]
+    out["max_abs_dK_mixed_vs_fp64_all"] = float(np.max(np.abs(kmx - k64)))
+    out["max_abs_K"] = float(np.max(np.abs(k64)))
+    if "fp64" in out and "mixed" in out:
+        out["speedup_mixed_vs_fp64"] = out["fp64"]["build_s"] / out["mixed"]["build_s"]
+    log(f"mixed vs FP64 on every element: {out['max_abs_dK_mixed_vs_fp64_all']:.3e}")
     o = oracle.Oracle(s64)
     blocks = o.blocks.astype(np.int64)
     pick = sample_blocks(s64, blocks, args.blocks)
-    assert np.array_equal(pick, z["pick"]), "the saved K is of other blocks"
+    sel = pick[::max(1, args.stride)]
     t = time.perf_counter()
-    o.schwarz_rows(np.concatenate([blocks[pick, 0], blocks[pick, 1]]))
+    o.schwarz_rows(np.concatenate([blocks[sel, 0], blocks[sel, 1]]))
     o.set_density(o.density_from_system())
-    Kref, nterms = o.build_K(blocks=pick)
+    Kref, nterms = o.build_K(blocks=sel)
     dt = time.perf_counter() - t
-    log(f"oracle: {len(pick)} K blocks, {nterms} ordered quartets, {dt:.1f} s")
-    per, a = [], 0
-    for b in pick:
-        n = int(o.offsets[b + 1] - o.offsets[b])
-        ref = Kref[o.offsets[b]:o.offsets[b + 1]]
+    log(f"oracle: {len(sel)} K blocks, {nterms} ordered quartets, {dt:.1f} s")
+    per = []
+    for b in sel:
+        a, e = o.offsets[b], o.offsets[b + 1]
+        ref = Kref[a:e]
         per.append({"block": [int(v) for v in blocks[b]], "max_abs_K": float(np.max(np.abs(ref))),
-                    "max_abs_dK_mixed": float(np.max(np.abs(z["kmx"][a:a + n] - ref))),
-                    "max_abs_dK_fp64": float(np.max(np.abs(z["k64"][a:a + n] - ref)))})
-        a += n
+                    "max_abs_dK_mixed": float(np.max(np.abs(kmx[a:e] - ref))),
+                    "max_abs_dK_fp64": float(np.max(np.abs(k64[a:e] - ref)))})
     out["oracle_blocks"] = per
     out["oracle_ordered_quartets"] = int(nterms)
     out["oracle_s"] = dt

@@ -136,3 +136,26 @@ def test_fused_multi_plan_build_in_chunks():
         assert np.max(np.abs(b - _oracle_K(s, d.cpu().numpy()))) <= 1e-10
     for p in plans:
         p.destroy()
+
+
+def test_progress_reports_every_chunk():
+    s = _tiny_cell(precision="mixed").with_(fp32_cutoff=1e-2)
+    plan = hfx.Plan(s)
+    D = torch.from_numpy(_density(s, plan.blocks)).to(DEV)
+    K = torch.zeros_like(D)
+    seen = []
+    plan.set_progress(lambda lst, chunk, done, total: seen.append((lst, chunk, done, total)))
+    plan.set_list_limit(3000)
+    info = plan.build_K(D, K, flags=hfx.HFX_SYNC, info=True)
+    assert len(seen) == info["n_chunks"] >= 4
+    assert [c for _, c, _, _ in seen] == list(range(1, len(seen) + 1))
+    for lst in (0, 1):
+        rep = [(d, t) for l_, _, d, t in seen if l_ == lst]
+        assert rep, lst
+        assert all(b[0] > a[0] for a, b in zip(rep, rep[1:]))
+        assert rep[-1][0] == rep[-1][1]
+    assert seen[-1][3] + [t for l_, _, d, t in seen if l_ == 0][-1] == info["n_quartets"]
+    plan.set_progress(None)
+    plan.build_K(D, K, flags=hfx.HFX_SYNC)
+    assert len(seen) == info["n_chunks"]
+    plan.destroy()

@@ -137,3 +137,54 @@ def test_step_budget_bounds_each_step_and_keeps_fifo():
     # and the budgeted schedule has a lower median latency than running everyone every step
     st_all, _ = _run(reqs, {r.rid: 1 for r in reqs}, 100, **work)
     assert st.latency_percentile(50) <= st_all.latency_percentile(50)
+
+
+def test_least_attained_service_lets_short_requests_past_a_long_one():
+    # request 0 costs far more than the step budget; the others are short
+    clock = VClock()
+
+    class Ex(HostExecutor):
+        def cost(self, st):
+            return 50.0 if st["r"].rid == 0 else 1.0
+
+    reqs = [ServeRequest(i, None, n_iter=4 if i == 0 else 2, arrival_s=0.001 * i) for i in range(6)]
+    fifo = Server(Ex(clock, {i: 1 for i in range(6)}, work_s=0.1), 100, step_budget=10.0, clock=clock,
+                  sleep=clock.sleep, policy="fifo").run(reqs)
+    clock.t = 0.0
+    las = Server(Ex(clock, {i: 1 for i in range(6)}, work_s=0.1), 100, step_budget=10.0, clock=clock,
+                 sleep=clock.sleep, policy="las").run(reqs)
+    lat = lambda st: {r.rid: r.latency_s for r in st.results}
+    lf, ll = lat(fifo), lat(las)
+    assert len(fifo.results) == len(las.results) == 6
+    # under FIFO every short request waits for the long one; under LAS none does
+    assert all(lf[i] > lf[0] * 0.9 for i in range(1, 6))
+    assert all(ll[i] < ll[0] for i in range(1, 6))
+    # the same work is done, and results do not depend on the policy
+    assert fifo.builds == las.builds
+    for a, b in zip(fifo.results, las.results):
+        assert np.array_equal(a.result, b.result)
+
+
+def test_stop_after_reports_unfinished_requests():
+    clock = VClock()
+    reqs = [ServeRequest(i, None, n_iter=5, arrival_s=0.5 * i) for i in range(8)]
+    ex = HostExecutor(clock, {i: 1 for i in range(8)})
+    st = Server(ex, 3, clock=clock, sleep=clock.sleep, stop_after_s=6.0).run(reqs)
+    assert st.unfinished and len(st.results) + len(st.unfinished) == 8
+    assert not ex.live  # cut-off requests were released
+    assert all(r.finished_s <= 6.0 + 10.0 for r in st.results)
+
+
+def test_shortest_remaining_work_first():
+    clock = VClock()
+
+    class Ex(HostExecutor):
+        def cost(self, st):
+            return 40.0 if st["r"].rid in (0, 2) else 1.0
+
+    reqs = [ServeRequest(i, None, n_iter=3, arrival_s=0.001 * i) for i in range(6)]
+    st = Server(Ex(clock, {i: 1 for i in range(6)}, work_s=0.1), 100, step_budget=5.0, clock=clock,
+                sleep=clock.sleep, policy="srpt").run(reqs)
+    lat = {r.rid: r.latency_s for r in st.results}
+    assert len(st.results) == 6
+    assert max(lat[i] for i in (1, 3, 4, 5)) < min(lat[0], lat[2])
