@@ -166,6 +166,10 @@ def bench_batch(args):
     ssmx = [x.with_(precision="mixed", fp32_cutoff=1e-6) for x in ss64]
     p64 = [hfx.Plan(x) for x in ss64]
     pmx = [hfx.Plan(x) for x in ssmx]
+    # the fused lists of all clusters (about 75 GB for the 512-cluster
+    # recipe) fit the device whole: no chunks, so the graph form can run
+    for p in p64 + pmx:
+        p.set_list_limit(args.batch_list_limit)
     Ds = [torch.from_numpy(_dens(x, p)).cuda() for x, p in zip(ss64, p64)]
     K_sep = [torch.zeros_like(d) for d in Ds]
     atoms = [x.n_atoms for x in ss64]
@@ -190,8 +194,10 @@ def bench_batch(args):
     print(f"# separate FP64: {sep:.2f} s, {nq} quartets", file=sys.stderr, flush=True)
     K_f = [torch.zeros_like(d) for d in Ds]
     for name, plans, Ks in (("fused_fp64", p64, K_f), ("fused_mixed", pmx, [torch.zeros_like(d) for d in Ds])):
+        t = time.perf_counter()
         hfx.build_K_multi(plans, Ds, Ks, flags=hfx.HFX_SYNC)  # sizes the fused lists
         torch.cuda.synchronize()
+        print(f"# {name}: first (sizing) build {time.perf_counter() - t:.2f} s", file=sys.stderr, flush=True)
         t = time.perf_counter()
         info = hfx.build_K_multi(plans, Ds, Ks, flags=hfx.HFX_SYNC, info=True)
         dt = time.perf_counter() - t
@@ -201,8 +207,10 @@ def bench_batch(args):
         if name == "fused_mixed":
             K_mx = Ks
             if info["n_chunks"] == 0:
+                print(f"# {name}: {dt:.2f} s; capturing the graph", file=sys.stderr, flush=True)
                 hfx.build_K_multi(plans, Ds, Ks, flags=hfx.HFX_GRAPH)  # capture
                 torch.cuda.synchronize()
+                print("# graph captured and replayed once", file=sys.stderr, flush=True)
                 t = time.perf_counter()
                 hfx.build_K_multi(plans, Ds, Ks, flags=hfx.HFX_GRAPH)
                 dg = time.perf_counter() - t
@@ -224,6 +232,74 @@ def bench_batch(args):
                                              f"atoms (heavy s,s,p,p,d / light s,s,p, 4 primitives, Coulomb), "
                                              f"{sum(atoms)} atoms in all"},
                       "forms": out}), flush=True)
+
+
+def bench_spin(args):
+    """Collinear spin on the 64-atom diamond workload: one spin build (both
+    densities, one ERI evaluation) against two plain FP64 builds, one per
+    spin density (the beta density: the alpha recipe with another seed,
+    scaled by 0.4)."""
+    import torch
+    import systems
+    from paper_2009_03555_amd import hfx
+    s = workload("config2", "fp64")
+    plan = hfx.Plan(s)
+    Da = torch.from_numpy(_dens(s, plan)).cuda()
+    Db = 0.4 * torch.from_numpy(_dens(s.with_(seed=s.seed + 17), plan)).cuda()
+    Ka, Kb, Ks_a, Ks_b = (torch.zeros_like(Da) for _ in range(4))
+    plan.build_K(Da, Ka, flags=hfx.HFX_SYNC)
+    torch.cuda.synchronize()
+    t = time.perf_counter()
+    ia = plan.build_K(Da, Ka, flags=hfx.HFX_SYNC, info=True)
+    ib = plan.build_K(Db, Kb, flags=hfx.HFX_SYNC, info=True)
+    two = time.perf_counter() - t
+    print(f"# two plain builds: {two:.2f} s", file=sys.stderr, flush=True)
+    plan.build_K_spin(Da, Db, Ks_a, Ks_b, flags=hfx.HFX_SYNC)
+    torch.cuda.synchronize()
+    t = time.perf_counter()
+    isp = plan.build_K_spin(Da, Db, Ks_a, Ks_b, flags=hfx.HFX_SYNC, info=True)
+    one = time.perf_counter() - t
+    print(f"# one spin build: {one:.2f} s", file=sys.stderr, flush=True)
+    out = {"two_plain_builds_s": two, "spin_build_s": one, "speedup": two / one,
+           "quartets_plain_alpha": ia["n_quartets"], "quartets_plain_beta": ib["n_quartets"],
+           "quartets_spin": isp["n_quartets"],
+           "max_abs_dK_spin_vs_plain": max(float(torch.max(torch.abs(Ks_a - Ka)).item()),
+                                           float(torch.max(torch.abs(Ks_b - Kb)).item()))}
+    plan.destroy()
+    print(json.dumps({"metric": "collinear-spin exchange build time", "unit": "s", "value": one,
+                      "higher_is_better": False, "n_gpus": 1, "data": "synthetic",
+                      "config": {"workload": s.name + " with two spin densities"}, "forms": out}), flush=True)
+
+
+def bench_kspace(args):
+    """k-space assembly of the HSE06 exchange Hamiltonian of the 64-atom
+    diamond workload from a K in the pattern layout, at --nk k-points."""
+    import torch
+    import systems
+    from paper_2009_03555_amd import hfx
+    s = workload("config2", "fp64")
+    plan = hfx.Plan(s)
+    K = torch.from_numpy(_dens(s, plan)).cuda()
+    nbf = s.n_functions()
+    rec = 2 * np.pi * np.linalg.inv(np.asarray(s.lattice)).T
+    kp = np.random.default_rng(5).uniform(-0.5, 0.5, size=(args.nk, 3)) @ rec
+    H = torch.empty((args.nk, nbf, nbf, 2), dtype=torch.float64, device="cuda")
+    plan.kspace(K, kp, 0.25, H)
+    torch.cuda.synchronize()
+    reps = 5
+    t = time.perf_counter()
+    for _ in range(reps):
+        plan.kspace(K, kp, 0.25, H)
+    torch.cuda.synchronize()
+    dt = (time.perf_counter() - t) / reps
+    # algorithmic bytes: H written once (16 B per complex element), K read
+    # once per k-point (8 B per value)
+    byt = args.nk * (16 * nbf * nbf + 8 * plan.nnz)
+    out = {"nk": args.nk, "nbf": nbf, "ms": dt * 1e3, "gb_per_s": byt / dt / 1e9, "bytes": byt}
+    plan.destroy()
+    print(json.dumps({"metric": "H^HFX(k) assembly time", "unit": "ms", "value": dt * 1e3,
+                      "higher_is_better": False, "n_gpus": 1, "data": "synthetic",
+                      "config": {"workload": f"{s.name}, {args.nk} k-points"}, "forms": out}), flush=True)
 
 
 def bench_serve(args):
@@ -341,6 +417,9 @@ def main():
     ap.add_argument("--hbm-gb", type=float, default=200.0, help="serve workload admission limit")
     ap.add_argument("--step-quartets", type=float, default=3e8,
                     help="serve workload: screened quartets one scheduler step may take on")
+    ap.add_argument("--nk", type=int, default=8, help="kspace workload: k-points")
+    ap.add_argument("--batch-list-limit", type=int, default=1 << 34,
+                    help="batch workload: quartets a fused list may hold (more run in chunks)")
     ap.add_argument("--copy-gib", type=float, default=0.0,
                     help="first run one plain device-to-device copy of this many GiB (a reference "
                          "dispatch of known traffic for hardware-counter runs)")
@@ -371,6 +450,10 @@ def main():
         return bench_batch(args)
     if args.workload == "serve":
         return bench_serve(args)
+    if args.workload == "spin":
+        return bench_spin(args)
+    if args.workload == "kspace":
+        return bench_kspace(args)
 
     prec = "fp64" if args.precision in ("fp64", "both") else "mixed"
     s = workload(args.workload, prec)

@@ -207,7 +207,7 @@ hfx_status hfx_kspace(hfx_plan_t plan, const double *k_dev, int32_t nk, const do
                       double *h_dev);
 
 /* Largest number of unique quartets a build of this plan holds in one
- * quartet list (8 bytes each; default 2^31, i.e. 16 GiB; 0 restores the
+ * quartet list (8 bytes each; default 2^33, i.e. 64 GiB; 0 restores the
  * default).  A screened list longer than this is evaluated in chunks: the
  * screening work items (one bra pair against one ket class) are cut into
  * consecutive ranges whose quartets fit, and each range is filled and run
@@ -254,7 +254,9 @@ hfx_status hfx_build_K_multi(int32_t n, const hfx_plan_t *plans, const double *c
  * encoding of hfx_export what = 1: bra pair | ket pair << 24 | translation
  * << 48, any order; duplicates are evaluated twice).  The quartet screening
  * predicate is not applied (the caller chose the quartets); the primitive-
- * quartet bound is, with P_scr from d_dev.  Synchronous.  HFX_ERR_INVALID if
+ * quartet bound is, with P_scr from d_dev; a mixed-precision plan sends the
+ * quartets below its FP32 cutoff to the FP32 kernels, as a build would.
+ * Synchronous.  HFX_ERR_INVALID if
  * a pair index is out of range or a quartet's bra pair class is below its
  * ket pair class. */
 hfx_status hfx_build_K_subset(hfx_plan_t plan, const double *d_dev, double *k_dev, const uint64_t *quartets_host,

@@ -131,8 +131,10 @@ eri_digest_kernel(const DevSys *__restrict__ sys, int nsys,
   const int64_t nthreads = (int64_t)gridDim.x * blockDim.x;
   const int64_t q0 = seg[0], q1 = seg[nsys];
   unsigned long long prims = 0;
+  int pl = 0;  // plan of the previous quartet
   for (int64_t qi = q0 + (int64_t)blockIdx.x * blockDim.x + threadIdx.x; qi < q1; qi += nthreads) {
-    const DevSys &s = sys[nsys > 1 ? plan_of(seg, nsys, qi) : 0];
+    pl = nsys > 1 ? plan_of_hint(seg, nsys, qi, pl) : 0;
+    const DevSys &s = sys[pl];
     const double *__restrict__ Dc = s.Dc;
     double *__restrict__ K4 = s.K4;
     const uint64_t q = list[qi];

@@ -217,8 +217,10 @@ void eri_lane_kernel(const DevSys *__restrict__ sys, int nsys,
   };
   unsigned long long prims = 0;
   const int64_t q0 = seg[0], q1 = seg[nsys];
+  int pl = 0;  // plan of the previous quartet
   for (int64_t qi = q0 + blockIdx.x; qi < q1; qi += gridDim.x) {
-    const DevSys &s = sys[nsys > 1 ? plan_of(seg, nsys, qi) : 0];
+    pl = nsys > 1 ? plan_of_hint(seg, nsys, qi, pl) : 0;
+    const DevSys &s = sys[pl];
     const uint64_t q = list[qi];
     const int bra = (int)(q & 0xFFFFFFull), ket = (int)((q >> 24) & 0xFFFFFFull);
     int g1, g2, g3;

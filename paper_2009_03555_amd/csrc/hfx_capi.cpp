@@ -36,8 +36,9 @@ hfx_status fail(hfx_status st, const std::string &msg) {
 constexpr uint32_t kMagic = 0x48465850u;  // "HFXP"
 constexpr double kPrimDrop = 1e-20;      // primitive-pair bound below which the ERI path skips it
 // quartets a list holds at once unless hfx_set_list_limit says otherwise
-// (16 GiB of list); longer lists are evaluated in chunks
-constexpr int64_t kDefaultMaxList = (int64_t)1 << 31;
+// (64 GiB of list, under a quarter of the device's 288 GB); longer lists
+// are evaluated in chunks
+constexpr int64_t kDefaultMaxList = (int64_t)1 << 33;
 
 bool lexpos(int a, int b, int c) { return a > 0 || (a == 0 && (b > 0 || (b == 0 && c >= 0))); }
 
@@ -1687,13 +1688,29 @@ hfx_status hfx_build_K_subset(hfx_plan_t plan, const double *d_dev, double *k_de
     if (cb < ck) return fail(HFX_ERR_INVALID, "quartet with bra pair class below its ket pair class");
     by[region_of(cb, ck)].push_back(q);
   }
-  std::vector<uint64_t> list;
-  std::vector<int64_t> seg(2 * kNQuartetClass);
-  for (int r = 0; r < kNQuartetClass; ++r) {
-    seg[2 * r] = (int64_t)list.size();
-    list.insert(list.end(), by[r].begin(), by[r].end());
-    seg[2 * r + 1] = (int64_t)list.size();
+  // mixed precision: a quartet whose Schwarz product is below the class's
+  // FP32 cutoff goes to the class's FP32 kernel, as in a full build
+  std::vector<double> Q;
+  if (P.precision == HFX_MIXED) {
+    Q.resize(npairs);
+    HIPCHK(hipMemcpyAsync(Q.data(), P.d_pr_Q, npairs * sizeof(double), hipMemcpyDeviceToHost, P.stream));
+    HIPCHK(hipStreamSynchronize(P.stream));
   }
+  std::vector<uint64_t> list;
+  std::vector<int64_t> seg(4 * kNQuartetClass);  // [region][FP64 part, FP32 part] bounds
+  for (int r = 0; r < kNQuartetClass; ++r)
+    for (int part = 0; part < 2; ++part) {
+      seg[4 * r + 2 * part] = (int64_t)list.size();
+      for (uint64_t q : by[r]) {
+        bool f32 = false;
+        if (!Q.empty()) {
+          const double qq = Q[q & 0xFFFFFFull] * Q[(q >> 24) & 0xFFFFFFull];
+          f32 = qq < P.ds.fp32_cut[r];
+        }
+        if (f32 == (part == 1)) list.push_back(q);
+      }
+      seg[4 * r + 2 * part + 1] = (int64_t)list.size();
+    }
   DevMem mem;
   uint64_t *d_list = nullptr;
   int64_t *d_seg = nullptr;
@@ -1712,10 +1729,13 @@ hfx_status hfx_build_K_subset(hfx_plan_t plan, const double *d_dev, double *k_de
   for (int cb = 0; cb < kNPairClass; ++cb)
     for (int ck = 0; ck <= cb; ++ck) {
       const int r = region_of(cb, ck);
-      const int64_t cnt = seg[2 * r + 1] - seg[2 * r];
-      if (cnt == 0) continue;
-      SegLaunch L{P.d_sys1, 1, d_seg + 2 * r, d_list, d_np + r, cnt, st, P.grid[r]};
-      launch_variant(P.kern[r], cb, ck, P.op, P.coop[r], L);
+      for (int part = 0; part < 2; ++part) {
+        const int64_t cnt = seg[4 * r + 2 * part + 1] - seg[4 * r + 2 * part];
+        if (cnt == 0) continue;
+        SegLaunch L{P.d_sys1, 1, d_seg + 4 * r + 2 * part, d_list, d_np + r, cnt, st,
+                    part ? P.grid32[r] : P.grid[r]};
+        launch_variant(part ? P.kern32[r] : P.kern[r], cb, ck, P.op, P.coop[r], L);
+      }
     }
   launch_finalize(P.ds, (int64_t)P.blocks.size(), P.d_blk_IJ, P.d_blk_off, P.d_partner, P.sph, P.d_K4, k_dev, st);
   hipError_t e = hipGetLastError();

@@ -167,6 +167,15 @@ __device__ __forceinline__ int plan_of(const int64_t *__restrict__ seg, int nsys
   return lo;
 }
 
+// plan_of for a thread whose quartet index only grows: the plan of its
+// previous quartet (hint) or the next one are checked first (one or two
+// cached loads instead of a binary search over the bounds)
+__device__ __forceinline__ int plan_of_hint(const int64_t *__restrict__ seg, int nsys, int64_t qi, int hint) {
+  if (qi < seg[hint + 1]) return hint;
+  if (hint + 2 <= nsys && qi < seg[hint + 2]) return hint + 1;
+  return plan_of(seg, nsys, qi);
+}
+
 __device__ __forceinline__ int img_index(const DevSys &s, int a, int b, int c);
 __device__ __forceinline__ int lookup(const DevSys &s, int I, int J, int a, int b, int c);
 

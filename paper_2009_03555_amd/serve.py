@@ -199,7 +199,8 @@ class HipExecutor:
     own one-plan batch and its share of a fused batch) + the densities and K
     (one allocation, rounded up to the 2 MiB segments of torch's caching
     allocator) + the quartet lists, sized from the screened count of the
-    first density (``hfx_screen_count``) with 25% headroom.  Sizing a
+    first density (``hfx_screen_count``) with 25% headroom, at most the list
+    limit per list (longer lists run in chunks).  Sizing a
     request makes a probe plan and uploads its first density; both are
     released before the request can be admitted, so that nothing of a
     waiting request stays on the device.  Requests whose static part alone
@@ -209,7 +210,11 @@ class HipExecutor:
 
     SEGMENT = 2 << 20
 
-    def __init__(self, keep_results: bool = True, flags: Optional[int] = None, list_headroom: float = 1.25):
+    def __init__(self, keep_results: bool = True, flags: Optional[int] = None, list_headroom: float = 1.25,
+                 list_limit: int = 1 << 33):
+        """list_limit: quartets a request's list holds at once (its plans are
+        set to it; a longer list runs in chunks, so the list memory charged
+        is at most this many quartets per list)."""
         from paper_2009_03555_amd import hfx
         import torch
         self.hfx = hfx
@@ -217,6 +222,7 @@ class HipExecutor:
         self.keep = keep_results
         self.flags = hfx.HFX_SYNC if flags is None else flags
         self.headroom = list_headroom
+        self.list_limit = int(list_limit)
         self._fp = {}
         self._nq = {}
         self.peak_device_bytes = 0
@@ -251,7 +257,8 @@ class HipExecutor:
         plan.destroy()
         del D0
         dk = -(-8 * nnz * (req.n_iter + 1) // self.SEGMENT) * self.SEGMENT
-        need = dev + dk + int(self.headroom * per_q * (n64 + n32))
+        lists = sum(min(int(self.headroom * n) + 4096, self.list_limit) for n in (n64, n32) if n)
+        need = dev + dk + per_q * lists
         self._fp[req.rid] = need
         self._nq[req.rid] = n64 + n32
         return need
@@ -259,6 +266,7 @@ class HipExecutor:
     def admit(self, req: ServeRequest):
         self.footprint(req)
         plan = self.hfx.Plan(req.system)
+        plan.set_list_limit(self.list_limit)
         D = self._densities(req, plan.blocks, range(req.n_iter))
         # densities of every iteration and K in one device allocation
         buf = self.torch.zeros((req.n_iter + 1, plan.nnz), dtype=self.torch.float64, device="cuda")

@@ -44,6 +44,8 @@ def main():
     ap.add_argument("--check", default="", help="host part only: oracle against the K saved by --gpu-out")
     ap.add_argument("--forms", nargs="+", default=["fp64", "mixed"], choices=["fp64", "mixed"],
                     help="GPU part: which builds to run (both are needed for the check)")
+    ap.add_argument("--oracle-cache", default="", help="host part: .npz holding (or to hold) the oracle's blocks")
+    ap.add_argument("--oracle-only", action="store_true", help="host part: only compute (and cache) the oracle")
     ap.add_argument("--stride", type=int, default=1,
                     help="host part: check every stride-th saved block only (the oracle needs minutes per block)")
     args = ap.parse_args()
@@ -114,8 +116,34 @@ def sample_blocks(system, blocks, n):
                                      rng.choice(near, half, replace=False)]))
 
 
-def check(args, s64, log):
+def oracle_blocks(args, s64, log):
+    """The oracle's K on the seeded sample of blocks (every stride-th), with
+    the Schwarz factors of only the rows they need; cached in
+    --oracle-cache if given (the oracle needs minutes per block here)."""
     import oracle
+    o = oracle.Oracle(s64)
+    blocks = o.blocks.astype(np.int64)
+    sel = sample_blocks(s64, blocks, args.blocks)[::max(1, args.stride)]
+    if args.oracle_cache and os.path.exists(args.oracle_cache):
+        z = np.load(args.oracle_cache)
+        if np.array_equal(z["sel"], sel):
+            log(f"oracle: {len(sel)} K blocks from {args.oracle_cache}")
+            return o, blocks, sel, z["K"], int(z["nterms"]), float(z["seconds"])
+    t = time.perf_counter()
+    o.schwarz_rows(np.concatenate([blocks[sel, 0], blocks[sel, 1]]))
+    o.set_density(o.density_from_system())
+    Kref, nterms = o.build_K(blocks=sel)
+    dt = time.perf_counter() - t
+    log(f"oracle: {len(sel)} K blocks, {nterms} ordered quartets, {dt:.1f} s")
+    if args.oracle_cache:
+        np.savez(args.oracle_cache, sel=sel, K=Kref, nterms=nterms, seconds=dt)
+    return o, blocks, sel, Kref, nterms, dt
+
+
+def check(args, s64, log):
+    o, blocks, sel, Kref, nterms, dt = oracle_blocks(args, s64, log)
+    if args.oracle_only:
+        return 0
     zs = {name: np.load(f"{args.check}_{name}.npz") for name in ("fp64", "mixed")}
     out = {}
     for name, z in zs.items():
@@ -126,16 +154,6 @@ def check(args, s64, log):
     if "fp64" in out and "mixed" in out:
         out["speedup_mixed_vs_fp64"] = out["fp64"]["build_s"] / out["mixed"]["build_s"]
     log(f"mixed vs FP64 on every element: {out['max_abs_dK_mixed_vs_fp64_all']:.3e}")
-    o = oracle.Oracle(s64)
-    blocks = o.blocks.astype(np.int64)
-    pick = sample_blocks(s64, blocks, args.blocks)
-    sel = pick[::max(1, args.stride)]
-    t = time.perf_counter()
-    o.schwarz_rows(np.concatenate([blocks[sel, 0], blocks[sel, 1]]))
-    o.set_density(o.density_from_system())
-    Kref, nterms = o.build_K(blocks=sel)
-    dt = time.perf_counter() - t
-    log(f"oracle: {len(sel)} K blocks, {nterms} ordered quartets, {dt:.1f} s")
     per = []
     for b in sel:
         a, e = o.offsets[b], o.offsets[b + 1]
@@ -144,6 +162,7 @@ def check(args, s64, log):
                     "max_abs_dK_mixed": float(np.max(np.abs(kmx[a:e] - ref))),
                     "max_abs_dK_fp64": float(np.max(np.abs(k64[a:e] - ref)))})
     out["oracle_blocks"] = per
+    out["oracle_K_blocks"] = len(sel)
     out["oracle_ordered_quartets"] = int(nterms)
     out["oracle_s"] = dt
     out["max_abs_dK_mixed_vs_oracle"] = max(p["max_abs_dK_mixed"] for p in per)

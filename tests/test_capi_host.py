@@ -82,3 +82,23 @@ def test_null_and_bogus_handles():
     assert L.hfx_plan_destroy(None) == hfx.HFX_ERR_STATE
     n = ctypes.c_int64(0)
     assert L.hfx_export(ctypes.c_void_p(12345), 0, None, ctypes.byref(n)) == hfx.HFX_ERR_STATE
+
+
+def test_translation_range_checked_at_plan_time():
+    # a cutoff long against the cell could need ket translations beyond the
+    # 5-bit quartet encoding: refused when planning, never dropped silently
+    s = systems.config2_diamond(n=(1, 1, 1), nprim=1, shells=(0,), r_cut=50.0)
+    with pytest.raises(hfx.HfxError) as e:
+        hfx.hfx_footprint(s)
+    assert e.value.status == hfx.HFX_ERR_UNSUPPORTED
+    assert "translations" in str(e.value)
+    # the benchmark cell is far inside the range
+    dev, per = hfx.hfx_footprint(systems.config2_diamond())
+    assert dev > 0 and per == 8
+
+
+def test_nao2gto_and_progress_symbols_are_host_callable():
+    # the fit needs no device: it runs here
+    r, R = systems.nao_radial(2, 1.1, 6.0)
+    e, c, rms = hfx.nao2gto_fit(2, r, R, 4)
+    assert np.all(np.diff(e) > 0) and rms < 0.05

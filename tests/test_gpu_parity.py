@@ -397,14 +397,19 @@ def test_full_size_list_on_sampled_bra_pairs():
     assert gk == ok, (len(gk - ok), len(ok - gk))
 
 
-def test_full_size_sampled_parity():
+@pytest.mark.parametrize("precision,cutoff", [("fp64", 0.0), ("mixed", 1e-4), ("mixed", 1e-6)])
+def test_full_size_sampled_parity(precision, cutoff):
     """The 64-atom periodic diamond workload of the benchmark at full size:
     K from a seeded, class-stratified sample of quartets (eight orbits of
     each of the 21 classes drawn from the plain loop, one member of each
     orbit in device orientation) on the GPU against the oracle's plain terms
-    of every member of the same orbits."""
+    of every member of the same orbits; FP64 (1e-10) and the mixed form at
+    the benchmark's cutoff 1e-4 and at 1e-6 (1e-7), the quartets below the
+    cutoff taking the FP32 kernels."""
     from tests.helpers import canonical_keys, gpu_rows, oracle_quartet_instances, orbit_members, to_gpu_quartets
-    s = systems.config2_diamond()
+    s = systems.config2_diamond(precision=precision)
+    if precision == "mixed":
+        s = s.with_(fp32_cutoff=cutoff)
     plan = hfx.Plan(s)
     o = oracle.Oracle(s)
     D = _density(s, plan.blocks)
@@ -437,10 +442,10 @@ def test_full_size_sampled_parity():
     plan.build_K_subset(Dd, Kd, q)
     Kref, used = o.K_from_quartets(orbit_members(rows))
     err = np.max(np.abs(Kd.cpu().numpy() - Kref))
-    print(f"full-size sample: {len(rows)} orbits, {used} ordered terms, max|dK| = {err:.3e}, "
-          f"max|K| = {np.max(np.abs(Kref)):.3e}")
+    print(f"full-size sample ({precision} {cutoff}): {len(rows)} orbits, {used} ordered terms, "
+          f"max|dK| = {err:.3e}, max|K| = {np.max(np.abs(Kref)):.3e}")
     assert used > len(rows)
-    assert err <= TOL_FP64
+    assert err <= (TOL_FP64 if precision == "fp64" else 1e-7)
 
 
 def test_max_primitives_and_angular_momentum():
