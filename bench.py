@@ -329,22 +329,30 @@ def bench_serve(args):
     win = args.serve_seconds
     limit = int(args.hbm_gb * 1e9)
     out = {"window_s": win, "requests_offered": args.n_requests}
+
+    def progress(rid, lst, chunk, done, total):
+        print(f"# request {rid} list {lst}: chunk {chunk}, {done}/{total} quartets", file=sys.stderr, flush=True)
+
     # offered work, from the probes of the executor the mixed server uses
-    exm = HipExecutor(keep_results=False)
+    exm = HipExecutor(keep_results=False, progress=progress)
     reqs_m = stream("mixed")
     t = time.perf_counter()
     offered = []
     for r in reqs_m:
         exm.footprint(r)
         offered.append(exm._nq[r.rid] * r.n_iter)
+        print(f"# probe {r.rid} ({r.system.name}): {exm._nq[r.rid]} quartets per build", file=sys.stderr,
+              flush=True)
     out["offered_quartets"] = int(sum(offered))
     out["offered_arrival_span_s"] = reqs_m[-1].arrival_s
     out["probe_s"] = time.perf_counter() - t
     print(f"# offered: {sum(offered):.3e} quartets over {reqs_m[-1].arrival_s:.3f} s of arrivals "
           f"(probes {out['probe_s']:.1f} s)", file=sys.stderr, flush=True)
     # plain: one request at a time, arrival order, inside the window
+    # the FP64 stream has the mixed one's requests: the executor's probe
+    # counts (per request id) serve every form
     reqs = stream("fp64")
-    ex = HipExecutor(keep_results=False)
+    ex = exm
     t0 = time.perf_counter()
     lat, builds, done, q = [], 0, 0, 0
     for r in reqs:
@@ -354,6 +362,8 @@ def bench_serve(args):
         if now < r.arrival_s:
             time.sleep(r.arrival_s - now)
         st = ex.admit(r)
+        print(f"# plain: request {r.rid} ({r.system.name}) admitted at {time.perf_counter() - t0:.1f} s",
+              file=sys.stderr, flush=True)
         finished = True
         for it in range(r.n_iter):
             if time.perf_counter() - t0 >= win:
@@ -372,11 +382,12 @@ def bench_serve(args):
                          "latency_ms_p50": float(np.percentile(lat, 50) * 1e3) if lat else None,
                          "latency_ms_p99": float(np.percentile(lat, 99) * 1e3) if lat else None}
     print(f"# plain fp64: {builds} builds, {done} requests done in {wall:.1f} s", file=sys.stderr, flush=True)
-    for prec, exe in (("mixed", exm), ("fp64", HipExecutor(keep_results=False))):
-        st = Server(exe, limit, step_budget=args.step_quartets, policy="srpt",
+    for prec in ("mixed", "fp64"):
+        exm.quartets_done = 0
+        st = Server(exm, limit, step_budget=args.step_quartets, policy="srpt",
                     stop_after_s=win).run(reqs_m if prec == "mixed" else stream("fp64"))
         d = st.summary()
-        d["quartets_per_s_est"] = exe.quartets_done / st.wall_s
+        d["quartets_per_s_est"] = exm.quartets_done / st.wall_s
         out[f"served_{prec}"] = d
         print(f"# served {prec}: {st.builds} builds, {len(st.results)} requests done in {st.wall_s:.1f} s",
               file=sys.stderr, flush=True)

@@ -91,7 +91,8 @@ typedef struct {
   int32_t precision;          /* hfx_precision */
   double fp32_cutoff;         /* HFX_MIXED: Q_IJ*Q_KL below this allows the FP32 path;
                                  classes whose FP32 kernel is no faster stay FP64:
-                                 (ss|ss) (ps|ss) (ps|ps) (pp|ps) (ds|ss) (dd|ss) */
+                                 (ss|ss) (ps|ss) (ps|ps) (pp|ps) (ds|ss) (dd|ss), and
+                                 (dd|dd), whose HRR amplifies FP32 rounding too much */
   int32_t spherical_d;        /* 1: five spherical d functions; 0: six Cartesian */
 } hfx_system;
 

@@ -547,21 +547,25 @@ bool variant_available(int cb, int ck, int v) {
 }
 bool variant_fp32(int v) { return v == K_REG32 || v == K_LANE32; }
 
-// Classes whose one-lane kernel gains nothing from the FP32 recursion
-// (measured on the 64-atom diamond recipe: (ss|ss), (ps|ss), (ps|ps), (pp|ps),
-// (ds|ss), (dd|ss) are Boys- and latency-bound, FP32 within 1% or slower);
-// their quartets stay on the FP64 list, which also saves a launch.
+// Classes kept on the FP64 list at any cutoff: those whose one-lane kernel
+// gains nothing from the FP32 recursion (measured on the 64-atom diamond
+// recipe: (ss|ss), (ps|ss), (ps|ps), (pp|ps), (ds|ss), (dd|ss) are Boys- and
+// latency-bound, FP32 within 1% or slower; this also saves a launch), and
+// (dd|dd), whose four HRR transfer steps scale the FP32 intermediates by
+// |AB|^2 |CD|^2 before they cancel: 46 of its quartets below Q_IJ Q_KL =
+// 1e-6 moved K by 1.0e-7 in a 25-atom cluster of the batch recipe (2.2e-9
+// with them in FP64).
 bool fp32_gains(int cb, int ck) {
   const int r = region_of(cb, ck);
   return !(r == region_of(0, 0) || r == region_of(1, 0) || r == region_of(1, 1) || r == region_of(2, 1) ||
-           r == region_of(3, 0) || r == region_of(5, 0));
+           r == region_of(3, 0) || r == region_of(5, 0) || r == region_of(5, 5));
 }
 
 // FP32-list kernel that goes with FP64-list kernel k64 (an FP64 variant:
 // the class does not split, see fp32_gains)
 int default_kern32(int cb, int ck, int k64) {
   if (k64 == K_REG && variant_available(cb, ck, K_REG32) && fp32_gains(cb, ck)) return K_REG32;
-  if (k64 == K_LANE) return K_LANE32;
+  if (k64 == K_LANE && fp32_gains(cb, ck)) return K_LANE32;
   return k64;
 }
 

@@ -200,7 +200,8 @@ class HipExecutor:
     (one allocation, rounded up to the 2 MiB segments of torch's caching
     allocator) + the quartet lists, sized from the screened count of the
     first density (``hfx_screen_count``) with 25% headroom, at most the list
-    limit per list (longer lists run in chunks).  Sizing a
+    limit per list (longer lists run in chunks).  Footprints and counts are
+    kept per request id, so one executor can serve a stream more than once.  Sizing a
     request makes a probe plan and uploads its first density; both are
     released before the request can be admitted, so that nothing of a
     waiting request stays on the device.  Requests whose static part alone
@@ -211,10 +212,12 @@ class HipExecutor:
     SEGMENT = 2 << 20
 
     def __init__(self, keep_results: bool = True, flags: Optional[int] = None, list_headroom: float = 1.25,
-                 list_limit: int = 1 << 33):
+                 list_limit: int = 1 << 33, progress: Optional[Callable] = None):
         """list_limit: quartets a request's list holds at once (its plans are
         set to it; a longer list runs in chunks, so the list memory charged
-        is at most this many quartets per list)."""
+        is at most this many quartets per list).  progress: called as
+        progress(rid, list, chunk, done, total) after every finished chunk of
+        a chunked build (fused builds report under their first request)."""
         from paper_2009_03555_amd import hfx
         import torch
         self.hfx = hfx
@@ -223,6 +226,7 @@ class HipExecutor:
         self.flags = hfx.HFX_SYNC if flags is None else flags
         self.headroom = list_headroom
         self.list_limit = int(list_limit)
+        self.progress = progress
         self._fp = {}
         self._nq = {}
         self.peak_device_bytes = 0
@@ -267,11 +271,13 @@ class HipExecutor:
         self.footprint(req)
         plan = self.hfx.Plan(req.system)
         plan.set_list_limit(self.list_limit)
+        if self.progress is not None:
+            plan.set_progress(lambda lst, chunk, done, total, rid=req.rid: self.progress(rid, lst, chunk, done, total))
         D = self._densities(req, plan.blocks, range(req.n_iter))
         # densities of every iteration and K in one device allocation
         buf = self.torch.zeros((req.n_iter + 1, plan.nnz), dtype=self.torch.float64, device="cuda")
         buf[: req.n_iter] = self.torch.from_numpy(np.stack(D)).cuda()
-        return {"req": req, "plan": plan, "buf": buf, "it": 0, "quartets": self._nq.pop(req.rid)}
+        return {"req": req, "plan": plan, "buf": buf, "it": 0, "quartets": self._nq[req.rid]}
 
     def cost(self, state) -> float:
         """work of one build of the request: its screened quartet count"""
@@ -291,6 +297,5 @@ class HipExecutor:
     def retire(self, state):
         out = state["buf"][-1].cpu().numpy() if self.keep else None
         state["plan"].destroy()
-        self._fp.pop(state["req"].rid, None)
         state["buf"] = None
         return out
