@@ -91,12 +91,13 @@ __device__ __forceinline__ void stage_prims(double *stage, int lane, int nbatch,
     const double *b = ppb + (int64_t)ib * kPP;
     const double *k = ppk + (int64_t)ik * kPP;
     const double zeta = b[0], eta = k[0];
-    const double ize = 1.0 / (zeta + eta);
+    const double rze = rsqrt_nr(zeta + eta);
+    const double ize = rze * rze;
     const double rho = zeta * eta * ize;
     const double PQx = b[1] - (k[1] + gx), PQy = b[2] - (k[2] + gy), PQz = b[3] - (k[3] + gz);
     const double T = rho * (PQx * PQx + PQy * PQy + PQz * PQz);
     // 2 pi^(5/2) / (zeta eta sqrt(zeta + eta)) times the pair factors
-    const double pref = b[7] * k[7] * sqrt(ize);
+    const double pref = b[7] * k[7] * rze;
     double G[L + 1];
     ladder<L, OP>(T, rho, s.omega2, pref, s.boys, G);
     const double fe = eta * ize, fz = zeta * ize;

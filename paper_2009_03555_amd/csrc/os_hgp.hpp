@@ -15,6 +15,19 @@
 
 namespace hfx {
 
+// 1/sqrt(x) for a positive normal x: the hardware estimate refined by two
+// Newton steps y <- y + y (1 - x y^2) / 2, each squaring the relative error,
+// to within a few ulp.  One of these replaces a correctly rounded division
+// and a square root (about twice the instructions) where a primitive
+// quartet needs both 1/x and 1/sqrt(x).
+__device__ __forceinline__ double rsqrt_nr(double x) {
+  double y = __builtin_amdgcn_rsq(x);
+  double e = fma(-x * y, y, 1.0);
+  y = fma(0.5 * y, e, y);
+  e = fma(-x * y, y, 1.0);
+  return fma(0.5 * y, e, y);
+}
+
 // ----------------------------------------------------------------- Boys
 // F_m(T), m = 0..L.  T < 40: eight-term Taylor series of F_L about the
 // nearest grid point (|dT| <= 1/32, truncation < 3e-17 relative), then the
@@ -53,11 +66,11 @@ __device__ __forceinline__ void boys_eval(double T, const double *__restrict__ t
       for (int m = L - 1; m >= 0; --m) F[m] = fma(t2, F[m + 1], e) * (1.0 / (2 * m + 1));
     }
   } else {
-    double r = 1.0 / T;
-    F[0] = sqrt(0.78539816339744830962 * r);  // (1/2) sqrt(pi / T)
+    const double y = rsqrt_nr(T);
+    F[0] = 0.88622692545275801365 * y;  // (1/2) sqrt(pi / T)
     if constexpr (L > 0) {
       double e = exp(-T);
-      double hr = 0.5 * r;
+      double hr = 0.5 * (y * y);
 #pragma unroll
       for (int m = 0; m < L; ++m) F[m + 1] = fma((double)(2 * m + 1), F[m], -e) * hr;
     }
@@ -70,10 +83,12 @@ __device__ __forceinline__ void ladder(double T, double rho, double omega2, doub
                                        const double *__restrict__ tab, double *G) {
   boys_eval<L>(T, tab, G);
   if constexpr (OP == 1) {
-    double s = omega2 / (omega2 + rho);
+    // s = omega^2 / (omega^2 + rho), sqrt(s) = omega / sqrt(omega^2 + rho)
+    const double r = rsqrt_nr(omega2 + rho);
+    double sp = sqrt(omega2) * r;
+    const double s = omega2 * (r * r);
     double Fs[L + 1];
     boys_eval<L>(s * T, tab, Fs);
-    double sp = sqrt(s);
 #pragma unroll
     for (int m = 0; m <= L; ++m) {
       G[m] = fma(-sp, Fs[m], G[m]);
@@ -326,12 +341,13 @@ __device__ __forceinline__ int prim_sum(const DevSys &s, const double *__restric
     for (int ib = 0; ib < nbe; ++ib) {
       const double *b = ppb + (int64_t)ib * kPP;
       const double zeta = b[0];
-      const double ize = 1.0 / (zeta + eta);
+      const double rze = rsqrt_nr(zeta + eta);
+      const double ize = rze * rze;
       const double rho = zeta * eta * ize;
       const double PQx = b[1] - Qx, PQy = b[2] - Qy, PQz = b[3] - Qz;
       const double T2 = rho * (PQx * PQx + PQy * PQy + PQz * PQz);
       // 2 pi^(5/2) / (zeta eta sqrt(zeta + eta)) K_ab K_cd
-      const double pref = b[7] * kk * sqrt(ize);
+      const double pref = b[7] * kk * rze;
       double G[L + 1];
       ladder<L, OP>(T2, rho, s.omega2, pref, s.boys, G);
       const double fe = eta * ize, fz = zeta * ize;
