@@ -312,11 +312,14 @@ def bench_serve(args):
     form gets the same wall-clock window (--serve-seconds) from the first
     arrival and reports what it finished in it:
     offered work (screened quartets of each request's first density, times
-    its iterations, from probe plans); plain FP64 (requests one at a time in
-    arrival order, one synchronised build per iteration); served (continuous
-    batching: fused builds of the admitted requests, each step within a
+    its iterations, from probe plans made with the requests' host densities
+    before any window); plain FP64 (requests one at a time in arrival order,
+    one synchronised build per iteration); served (continuous batching:
+    fused builds of the admitted requests, each step within a
     --step-quartets budget in shortest-remaining-work order), FP64 and mixed
-    precision.  Latency is from arrival to the last iteration's K."""
+    precision.  No form starts a build that, at the rate it has shown so
+    far, would end after its window.  Latency is from arrival to the last
+    iteration's K."""
     import torch
     import systems
     from paper_2009_03555_amd import hfx
@@ -333,13 +336,15 @@ def bench_serve(args):
     def progress(rid, lst, chunk, done, total):
         print(f"# request {rid} list {lst}: chunk {chunk}, {done}/{total} quartets", file=sys.stderr, flush=True)
 
-    # offered work, from the probes of the executor the mixed server uses
-    exm = HipExecutor(keep_results=False, progress=progress)
+    # offered work, from the probes of the executor every form uses; the
+    # requests' host densities are made here too, before the timed windows
+    # (they stand for what an SCF code hands over with each request)
+    exm = HipExecutor(keep_results=False, progress=progress, cache_host=True)
     reqs_m = stream("mixed")
     t = time.perf_counter()
     offered = []
     for r in reqs_m:
-        exm.footprint(r)
+        exm.prepare(r)
         offered.append(exm._nq[r.rid] * r.n_iter)
         print(f"# probe {r.rid} ({r.system.name}): {exm._nq[r.rid]} quartets per build", file=sys.stderr,
               flush=True)
@@ -348,16 +353,23 @@ def bench_serve(args):
     out["probe_s"] = time.perf_counter() - t
     print(f"# offered: {sum(offered):.3e} quartets over {reqs_m[-1].arrival_s:.3f} s of arrivals "
           f"(probes {out['probe_s']:.1f} s)", file=sys.stderr, flush=True)
-    # plain: one request at a time, arrival order, inside the window
+    # plain: one request at a time, arrival order, inside the window; a
+    # build is not started when, at the rate of the plain builds so far, it
+    # would end after the window (the queue's head then blocks the rest)
     # the FP64 stream has the mixed one's requests: the executor's probe
     # counts (per request id) serve every form
     reqs = stream("fp64")
     ex = exm
     t0 = time.perf_counter()
     lat, builds, done, q = [], 0, 0, 0
+    bq, bt = 0, 0.0  # quartets and seconds of the plain builds (rate)
+    blocked = None
     for r in reqs:
         now = time.perf_counter() - t0
         if now >= win:
+            break
+        if bt > 0 and now + exm._nq[r.rid] * bt / bq > win:
+            blocked = r.rid
             break
         if now < r.arrival_s:
             time.sleep(r.arrival_s - now)
@@ -366,19 +378,26 @@ def bench_serve(args):
               file=sys.stderr, flush=True)
         finished = True
         for it in range(r.n_iter):
-            if time.perf_counter() - t0 >= win:
+            now = time.perf_counter() - t0
+            if now >= win or (bt > 0 and now + st["quartets"] * bt / bq > win):
                 finished = False
+                blocked = r.rid
                 break
+            tb = time.perf_counter()
             st["plan"].build_K(st["buf"][it], st["buf"][-1], flags=hfx.HFX_SYNC)
+            bt += time.perf_counter() - tb
+            bq += st["quartets"]
             builds += 1
             q += st["quartets"]
         ex.retire(st)
         if finished:
             done += 1
             lat.append(time.perf_counter() - t0 - r.arrival_s)
+        if blocked is not None:
+            break
     wall = time.perf_counter() - t0
     out["plain_fp64"] = {"builds": builds, "builds_per_s": builds / wall, "quartets_per_s_est": q / wall,
-                         "requests_done": done, "wall_s": wall,
+                         "requests_done": done, "wall_s": wall, "blocked_by_request": blocked,
                          "latency_ms_p50": float(np.percentile(lat, 50) * 1e3) if lat else None,
                          "latency_ms_p99": float(np.percentile(lat, 99) * 1e3) if lat else None}
     print(f"# plain fp64: {builds} builds, {done} requests done in {wall:.1f} s", file=sys.stderr, flush=True)

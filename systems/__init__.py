@@ -16,6 +16,7 @@ from .generate import (  # noqa: F401
     random_cluster,
     diamond_supercell,
     density_blocks,
+    density_series,
     perturb_density,
     splitmix64,
     hash_uniform,

@@ -333,16 +333,22 @@ def density_blocks(system: System, blocks: np.ndarray, iteration: int = 0,
     are D_0 * prod_{t=1..k} (1 + noise * xi_t) with xi_t standard normal,
     symmetric in (i, j, n) <-> (j, i, -n).
     """
+    return density_series(system, blocks, iteration + 1, noise, first=iteration)[0]
+
+
+def density_series(system: System, blocks: np.ndarray, n_iter: int, noise: float = 1e-3,
+                   first: int = 0) -> List[List[np.ndarray]]:
+    """density_blocks for iterations first .. n_iter-1 in one pass (each
+    iteration's factor drawn once, the running product kept), the same
+    values bit for bit."""
     blocks = np.asarray(blocks, dtype=np.int64).reshape(-1, 5)
     nf = system.shell_nfunc()
     off = system.shell_func_offset()
     xyz = system.atom_xyz
-    out = []
-    # vectorise over all elements of all blocks
     sizes = nf[blocks[:, 0]] * nf[blocks[:, 1]]
     tot = int(sizes.sum())
     if tot == 0:
-        return [np.zeros((nf[b[0]], nf[b[1]])) for b in blocks]
+        return [[np.zeros((nf[b[0]], nf[b[1]])) for b in blocks] for _ in range(first, n_iter)]
     bi = np.repeat(np.arange(blocks.shape[0]), sizes)
     start = np.concatenate([[0], np.cumsum(sizes)[:-1]])
     local = np.arange(tot) - start[bi]
@@ -359,16 +365,22 @@ def density_blocks(system: System, blocks: np.ndarray, iteration: int = 0,
     rvec = xyz[system.shell_atom[I]] - (xyz[system.shell_atom[J]] + _image_vectors(system, img))
     r = np.sqrt(np.sum(rvec * rvec, axis=1))
     val = u * np.exp(-system.d_decay * r)
-    for k in range(1, iteration + 1):
-        u1 = hash_uniform(system.seed ^ 0x5A5A5A5A, k, ci, cj, cn[:, 0], cn[:, 1], cn[:, 2])
-        u2 = hash_uniform(system.seed ^ 0x3C3C3C3C, k, ci, cj, cn[:, 0], cn[:, 1], cn[:, 2])
-        xi = np.sqrt(-2.0 * np.log1p(-u1)) * np.cos(2.0 * np.pi * u2)
-        val = val * (1.0 + noise * xi)
-    val = np.where(np.abs(val) < system.d_drop, 0.0, val)
-    for k in range(blocks.shape[0]):
-        s = int(start[k])
-        out.append(val[s:s + int(sizes[k])].reshape(int(nf[blocks[k, 0]]), int(nf[blocks[k, 1]])))
-    return out
+    series = []
+    for k in range(0, n_iter):
+        if k >= 1:
+            u1 = hash_uniform(system.seed ^ 0x5A5A5A5A, k, ci, cj, cn[:, 0], cn[:, 1], cn[:, 2])
+            u2 = hash_uniform(system.seed ^ 0x3C3C3C3C, k, ci, cj, cn[:, 0], cn[:, 1], cn[:, 2])
+            xi = np.sqrt(-2.0 * np.log1p(-u1)) * np.cos(2.0 * np.pi * u2)
+            val = val * (1.0 + noise * xi)
+        if k < first:
+            continue
+        kept = np.where(np.abs(val) < system.d_drop, 0.0, val)
+        out = []
+        for q in range(blocks.shape[0]):
+            s0 = int(start[q])
+            out.append(kept[s0:s0 + int(sizes[q])].reshape(int(nf[blocks[q, 0]]), int(nf[blocks[q, 1]])))
+        series.append(out)
+    return series
 
 
 def perturb_density(system: System, blocks: np.ndarray, iteration: int) -> List[np.ndarray]:

@@ -188,3 +188,29 @@ def test_shortest_remaining_work_first():
     lat = {r.rid: r.latency_s for r in st.results}
     assert len(st.results) == 6
     assert max(lat[i] for i in (1, 3, 4, 5)) < min(lat[0], lat[2])
+
+
+def test_stop_time_keeps_out_requests_that_would_overrun_it():
+    # a long request (cost 100) behind short ones: with a stop time, SRPT
+    # runs the short ones, then leaves out the long one once the rate of the
+    # finished steps says it would end after the stop time
+    clock = VClock()
+
+    class Ex(HostExecutor):
+        def cost(self, st):
+            return 100.0 if st["r"].rid == 0 else 1.0
+
+    # the long request arrives just after the short ones: the first step
+    # (short ones only) gives the rate
+    reqs = [ServeRequest(i, None, n_iter=2, arrival_s=0.003 if i == 0 else 0.0) for i in range(4)]
+    ex = Ex(clock, {i: 1 for i in range(4)}, step_s=0.0, per_req_s=0.0, work_s=0.1)
+    st = Server(ex, 100, step_budget=5.0, clock=clock, sleep=clock.sleep, policy="srpt",
+                stop_after_s=3.0).run(reqs)
+    assert sorted(r.rid for r in st.results) == [1, 2, 3]
+    assert st.unfinished == [0]
+    assert st.wall_s <= 3.0 and not ex.live
+    # without a stop time the long request runs to the end
+    clock2 = VClock()
+    st2 = Server(Ex(clock2, {i: 1 for i in range(4)}, step_s=0.0, per_req_s=0.0, work_s=0.1), 100,
+                 step_budget=5.0, clock=clock2, sleep=clock2.sleep, policy="srpt").run(reqs)
+    assert len(st2.results) == 4
