@@ -396,7 +396,10 @@ def bench_serve(args):
         if blocked is not None:
             break
     wall = time.perf_counter() - t0
-    out["plain_fp64"] = {"builds": builds, "builds_per_s": builds / wall, "quartets_per_s_est": q / wall,
+    # every form is charged the whole window (a form that stops early,
+    # blocked or out of work that fits, has used it)
+    span = max(wall, win)
+    out["plain_fp64"] = {"builds": builds, "builds_per_s": builds / span, "quartets_per_s_est": q / span,
                          "requests_done": done, "wall_s": wall, "blocked_by_request": blocked,
                          "latency_ms_p50": float(np.percentile(lat, 50) * 1e3) if lat else None,
                          "latency_ms_p99": float(np.percentile(lat, 99) * 1e3) if lat else None}
@@ -406,7 +409,9 @@ def bench_serve(args):
         st = Server(exm, limit, step_budget=args.step_quartets, policy="srpt",
                     stop_after_s=win).run(reqs_m if prec == "mixed" else stream("fp64"))
         d = st.summary()
-        d["quartets_per_s_est"] = exm.quartets_done / st.wall_s
+        span = max(st.wall_s, win)
+        d["builds_per_s"] = st.builds / span
+        d["quartets_per_s_est"] = exm.quartets_done / span
         out[f"served_{prec}"] = d
         print(f"# served {prec}: {st.builds} builds, {len(st.results)} requests done in {st.wall_s:.1f} s",
               file=sys.stderr, flush=True)
@@ -512,7 +517,8 @@ def main():
             state["out"]["mixed"] = state["mixed"]
         if state.get("cpu") is not None:
             state["out"]["cpu_baseline"] = state["cpu"]
-        print(json.dumps(state["out"]), flush=True)
+        # provisional line of the steps so far (stderr: stdout gets one line)
+        print("# provisional: " + json.dumps(state["out"]), file=sys.stderr, flush=True)
 
     first = {}
 

@@ -128,24 +128,41 @@ class Server:
         builds = 0
         max_conc = 0
         qi = 0
+        waiting: List[ServeRequest] = []   # arrived, not admitted
         stopped = False
         cost_done, step_time = 0.0, 0.0  # for the rate of the deadline test
-        while qi < len(queue) or active:
+        by_work = self.policy != "fifo" and hasattr(self.ex, "request_work")
+        while qi < len(queue) or waiting or active:
             now = self.clock() - t0
             if self.stop_after > 0 and now >= self.stop_after:
                 stopped = True
                 break
-            # admit arrived requests in FIFO order while they fit
-            while (qi < len(queue) and queue[qi].arrival_s <= now and len(active) < self.max_batch):
-                need = self.ex.footprint(queue[qi])
-                if reserved + need > self.limit:
+            while qi < len(queue) and queue[qi].arrival_s <= now:
+                waiting.append(queue[qi])
+                qi += 1
+            # admission while they fit: FIFO stops at the first request that
+            # does not fit; "las" and "srpt" (with an executor that tells a
+            # request's work) take the arrived requests with the least work
+            # first and pass over those that do not fit, so that large
+            # requests do not hold the memory that small ones could run in
+            order = sorted(waiting, key=lambda r: (self.ex.request_work(r), r.arrival_s, r.rid)) if by_work \
+                else list(waiting)
+            for r in order:
+                if len(active) >= self.max_batch:
                     break
-                st = self.ex.admit(queue[qi])
+                need = self.ex.footprint(r)
+                if reserved + need > self.limit:
+                    if by_work:
+                        continue
+                    break
+                st = self.ex.admit(r)
                 reserved += need
                 peak = max(peak, reserved)
-                active.append([queue[qi], st, need, 0, now, [], 0.0])
-                qi += 1
+                active.append([r, st, need, 0, now, [], 0.0])
+                waiting.remove(r)
             if not active:
+                if waiting:
+                    raise ValueError(f"request {waiting[0].rid} needs more device memory than the limit")
                 # idle until the next arrival
                 self.sleep(max(0.0, queue[qi].arrival_s - (self.clock() - t0)))
                 continue
@@ -199,7 +216,8 @@ class Server:
             active = still
         wall = self.clock() - t0
         results.sort(key=lambda r: r.rid)
-        unfinished = [a[0].rid for a in active] + [r.rid for r in queue[qi:]] if stopped else []
+        unfinished = sorted([a[0].rid for a in active] + [r.rid for r in waiting] + [r.rid for r in queue[qi:]]) \
+            if stopped else []
         for a in active:
             self.ex.retire(a[1])
         return ServeStats(results, wall, n_steps, builds, max_conc, peak, unfinished)
@@ -312,6 +330,12 @@ class HipExecutor:
     def cost(self, state) -> float:
         """work of one build of the request: its screened quartet count"""
         return float(state["quartets"])
+
+    def request_work(self, req: ServeRequest) -> float:
+        """work of a whole request before admission: the screened quartet
+        count of its first density (from its probe) times its iterations"""
+        self.footprint(req)
+        return float(self._nq[req.rid]) * req.n_iter
 
     def step(self, states) -> None:
         plans = [s["plan"] for s in states]

@@ -214,3 +214,46 @@ def test_stop_time_keeps_out_requests_that_would_overrun_it():
     st2 = Server(Ex(clock2, {i: 1 for i in range(4)}, step_s=0.0, per_req_s=0.0, work_s=0.1), 100,
                  step_budget=5.0, clock=clock2, sleep=clock2.sleep, policy="srpt").run(reqs)
     assert len(st2.results) == 4
+
+
+def test_srpt_admission_passes_over_large_requests():
+    # request 0 arrives first and would take most of the memory: FIFO
+    # admission lets it hold the memory; shortest-work admission admits the
+    # small requests first and request 0 once there is room
+    clock = VClock()
+
+    class Ex(HostExecutor):
+        def cost(self, st):
+            return 50.0 if st["r"].rid == 0 else 1.0
+
+        def request_work(self, r):
+            return (50.0 if r.rid == 0 else 1.0) * r.n_iter
+
+    fp = {0: 8, **{i: 2 for i in range(1, 6)}}
+    reqs = [ServeRequest(i, None, n_iter=3, arrival_s=0.0 if i == 0 else 0.001) for i in range(6)]
+    st = Server(Ex(clock, fp, step_s=0.0, per_req_s=0.0, work_s=0.1), 10, step_budget=5.0, clock=clock,
+                sleep=clock.sleep, policy="srpt").run(reqs)
+    lat = {r.rid: r.latency_s for r in st.results}
+    assert len(st.results) == 6
+    assert max(lat[i] for i in range(1, 6)) < lat[0]
+    assert st.peak_reserved_bytes <= 10
+    # FIFO admission: request 0 is admitted first and the others queue behind it
+    clock2 = VClock()
+    st2 = Server(Ex(clock2, fp, step_s=0.0, per_req_s=0.0, work_s=0.1), 10, step_budget=5.0, clock=clock2,
+                 sleep=clock2.sleep, policy="fifo").run(reqs)
+    lat2 = {r.rid: r.latency_s for r in st2.results}
+    assert min(lat2[i] for i in range(1, 6)) > min(lat[i] for i in range(1, 6))
+
+
+def test_request_larger_than_the_limit_after_probing_is_an_error():
+    clock = VClock()
+
+    class Ex(HostExecutor):
+        def static_footprint(self, r):
+            return 1
+
+        def footprint(self, r):
+            return 100
+
+    with pytest.raises(ValueError):
+        Server(Ex(clock, {0: 1}), 10, clock=clock, sleep=clock.sleep).run([ServeRequest(0, None, 2, 0.0)])
