@@ -632,12 +632,14 @@ def _line(args, s, plan, prec, lat, infos, total, w_done, labels):
 
 
 def kernel_hash():
-    """Hash of the ERI kernel sources (traffic counters are valid only for it)."""
+    """Hash of the sources the ERI class kernels are compiled from (their
+    translation units eri_*.hip and every header); traffic counters are
+    valid only for it.  The auxiliary kernels (k_aux.hip) are not part of it."""
     import hashlib
     h = hashlib.sha256()
     d = os.path.join(ROOT, "paper_2009_03555_amd", "csrc")
     for f in sorted(os.listdir(d)):
-        if f.endswith((".hpp", ".hip")):
+        if f.endswith(".hpp") or (f.startswith("eri_") and f.endswith(".hip")):
             h.update(open(os.path.join(d, f), "rb").read())
     return h.hexdigest()[:16]
 

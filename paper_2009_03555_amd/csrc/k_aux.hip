@@ -531,47 +531,30 @@ __global__ __launch_bounds__(64) void kspace_kernel(DevSys s, const int4 *__rest
                                                     const int32_t *__restrict__ func_off, int sph,
                                                     const double *__restrict__ K, const double *__restrict__ kpts,
                                                     int nk, int64_t nbf, double scale, double *__restrict__ H) {
-  // one block per (shell pair, k-point); the phase of an image block is the
-  // same for all its elements, so the lanes first compute the phases of up
-  // to 64 image blocks (one sincos each) into LDS, then each lane sums its
-  // element over them
-  __shared__ double ph_re[64], ph_im[64];
   const int p = blockIdx.x;
   const int k = blockIdx.y;
-  if (p >= npairs || k >= nk) return;  // uniform over the block
+  if (p >= npairs || k >= nk) return;
   const int4 pr = pairs[p];  // I, J, first block, block count
   const int I = pr.x, J = pr.y;
   const int ni = nfunc_dev(s.sh_l[I], sph), nj = nfunc_dev(s.sh_l[J], sph);
-  const int lane = threadIdx.x;
-  const int e = lane;
+  const int e = threadIdx.x;
+  if (e >= ni * nj) return;
   const double kx = kpts[3 * k], ky = kpts[3 * k + 1], kz = kpts[3 * k + 2];
   const double dx = s.sh_xyz[3 * J] - s.sh_xyz[3 * I], dy = s.sh_xyz[3 * J + 1] - s.sh_xyz[3 * I + 1],
                dz = s.sh_xyz[3 * J + 2] - s.sh_xyz[3 * I + 2];
   double re = 0.0, im = 0.0;
-  for (int b0 = pr.z; b0 < pr.z + pr.w; b0 += 64) {
-    const int nb = (pr.z + pr.w - b0) < 64 ? (pr.z + pr.w - b0) : 64;
-    if (lane < nb) {
-      int n1, n2, n3;
-      unpack_img8(blk_img[b0 + lane], n1, n2, n3);
-      const double tx = n1 * s.lat[0] + n2 * s.lat[3] + n3 * s.lat[6] + dx;
-      const double ty = n1 * s.lat[1] + n2 * s.lat[4] + n3 * s.lat[7] + dy;
-      const double tz = n1 * s.lat[2] + n2 * s.lat[5] + n3 * s.lat[8] + dz;
-      double sn, cs;
-      sincos(kx * tx + ky * ty + kz * tz, &sn, &cs);
-      ph_re[lane] = cs;
-      ph_im[lane] = sn;
-    }
-    __syncthreads();
-    if (e < ni * nj) {
-      for (int t = 0; t < nb; ++t) {
-        const double v = K[blk_off[b0 + t] + e];
-        re = fma(v, ph_re[t], re);
-        im = fma(v, ph_im[t], im);
-      }
-    }
-    __syncthreads();  // the phases are rewritten by the next group of blocks
+  for (int b = pr.z; b < pr.z + pr.w; ++b) {
+    int n1, n2, n3;
+    unpack_img8(blk_img[b], n1, n2, n3);
+    const double tx = n1 * s.lat[0] + n2 * s.lat[3] + n3 * s.lat[6] + dx;
+    const double ty = n1 * s.lat[1] + n2 * s.lat[4] + n3 * s.lat[7] + dy;
+    const double tz = n1 * s.lat[2] + n2 * s.lat[5] + n3 * s.lat[8] + dz;
+    double sn, cs;
+    sincos(kx * tx + ky * ty + kz * tz, &sn, &cs);
+    const double v = K[blk_off[b] + e];
+    re = fma(v, cs, re);
+    im = fma(v, sn, im);
   }
-  if (e >= ni * nj) return;
   const int m = e / nj, n = e - m * nj;
   const int64_t row = func_off[I] + m, col = func_off[J] + n;
   double *h = H + 2 * (((int64_t)k * nbf + row) * nbf + col);
