@@ -567,6 +567,8 @@ def main():
     if not args.no_cpu_baseline:
         cpu_s = max(2.0, min(args.cpu_seconds, deadline - time.perf_counter() - 5.0))
         state["cpu"] = cpu_baseline(s, cpu_s)
+        # extrapolated, not measured: one whole build at the sampled rate
+        state["cpu"]["full_build_s_extrapolated"] = infos[-1]["n_quartets"] / state["cpu"]["value"]
         out["cpu_baseline"] = state["cpu"]
     print(json.dumps(out), flush=True)
 
