@@ -47,14 +47,14 @@ def class_labels():
 
 def workload(name: str, precision: str):
     import systems
-    if name == "config2":
-        return systems.config2_diamond(precision=precision)
-    if name == "config2_cell8":
-        return systems.config2_diamond(n=(1, 1, 1), precision=precision, name="config2_recipe_diamond8")
-    if name == "config1":
-        return systems.config1_molecule()
-    if name == "config3":
-        return systems.config3_cluster(precision=precision)
+    if name == "diamond64":
+        return systems.diamond_cell(precision=precision)
+    if name == "diamond8":
+        return systems.diamond_cell(n=(1, 1, 1), precision=precision)
+    if name == "molecule8":
+        return systems.molecule8()
+    if name == "cluster256":
+        return systems.cluster_k4(precision=precision)
     raise SystemExit(f"unknown workload {name}")
 
 
@@ -162,7 +162,7 @@ def bench_batch(args):
     import systems
     from paper_2009_03555_amd import hfx
     out = {}
-    ss64 = systems.config4_batch(n_clusters=args.n_clusters, n_range=tuple(args.cluster_atoms), precision="fp64")
+    ss64 = systems.cluster_batch(n_clusters=args.n_clusters, n_range=tuple(args.cluster_atoms), precision="fp64")
     ssmx = [x.with_(precision="mixed", fp32_cutoff=1e-6) for x in ss64]
     p64 = [hfx.Plan(x) for x in ss64]
     pmx = [hfx.Plan(x) for x in ssmx]
@@ -242,7 +242,7 @@ def bench_spin(args):
     import torch
     import systems
     from paper_2009_03555_amd import hfx
-    s = workload("config2", "fp64")
+    s = workload("diamond64", "fp64")
     plan = hfx.Plan(s)
     Da = torch.from_numpy(_dens(s, plan)).cuda()
     Db = 0.4 * torch.from_numpy(_dens(s.with_(seed=s.seed + 17), plan)).cuda()
@@ -277,7 +277,7 @@ def bench_kspace(args):
     import torch
     import systems
     from paper_2009_03555_amd import hfx
-    s = workload("config2", "fp64")
+    s = workload("diamond64", "fp64")
     plan = hfx.Plan(s)
     K = torch.from_numpy(_dens(s, plan)).cuda()
     nbf = s.n_functions()
@@ -326,7 +326,7 @@ def bench_serve(args):
     from paper_2009_03555_amd.serve import HipExecutor, Server, ServeRequest
 
     def stream(prec):
-        rq = systems.config5_requests(n_requests=args.n_requests, rate_per_s=args.rate, precision=prec)
+        rq = systems.request_stream(n_requests=args.n_requests, rate_per_s=args.rate, precision=prec)
         return [ServeRequest(r.rid, r.system, r.n_iter, r.arrival_s) for r in rq]
 
     win = args.serve_seconds
@@ -431,7 +431,7 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=1)
     ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--workload", default="config2")
+    ap.add_argument("--workload", default="diamond64")
     ap.add_argument("--precision", default="both", choices=["fp64", "mixed", "both"],
                     help="fp64: the plain form only; both: also the mixed-precision form, its "
                          "throughput and max|dK| against the FP64 build")

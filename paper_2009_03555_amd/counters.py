@@ -4,7 +4,7 @@ Usage (after the two passes of ``bench.py ... --copy-gib 1``, one with
 ``rocprofv3 --pmc FETCH_SIZE`` and one with ``--pmc WRITE_SIZE``):
 
     python -m paper_2009_03555_amd.counters FETCH_DIR WRITE_DIR \\
-        --workload config2 --out profiles/traffic.json
+        --workload diamond64 --out profiles/traffic.json
 
 Each pass's counter CSV (``*counter_collection.csv`` under the directory)
 gives FETCH_SIZE / WRITE_SIZE in KiB per dispatch.  The reference dispatch
@@ -65,7 +65,7 @@ def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("fetch_dir")
     ap.add_argument("write_dir")
-    ap.add_argument("--workload", default="config2")
+    ap.add_argument("--workload", default="diamond64")
     ap.add_argument("--copy-gib", type=float, default=1.0)
     ap.add_argument("--out", default=os.path.join(ROOT, "profiles", "traffic.json"))
     args = ap.parse_args()

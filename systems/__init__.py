@@ -8,11 +8,11 @@ from a counter-based hash (SplitMix64) keyed by the quantity it belongs to.
 """
 from .generate import (  # noqa: F401
     System,
-    config1_molecule,
-    config2_diamond,
-    config3_cluster,
-    config4_batch,
-    config5_requests,
+    molecule8,
+    diamond_cell,
+    cluster_k4,
+    cluster_batch,
+    request_stream,
     random_cluster,
     diamond_supercell,
     density_blocks,

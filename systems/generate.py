@@ -2,25 +2,25 @@
 
 Recipes (all lengths in bohr, exponents in bohr^-2):
 
-* ``config1_molecule``: 8 atoms uniform in a 10-bohr cube (min separation 2),
+* ``molecule8``: 8 atoms uniform in a 10-bohr cube (min separation 2),
   one element with shells s,s,p, 3 primitives per shell, exponents
   log-uniform in [0.1, 10], raw coefficients uniform in [0.1, 1]; bare
   Coulomb; tau = 1e-10; density D_ij = u_ij exp(-0.3 r_ij).
-* ``config2_diamond``: conventional diamond cell a = 10.26 repeated 2x2x2
+* ``diamond_cell``: conventional diamond cell a = 10.26 repeated 2x2x2
   (64 atoms, cubic cell edge 20.52), one element with shells s,s,p,p,d
   (13 spherical functions), 6 primitives per shell, exponents log-uniform in
   [0.05, 20]; erfc-screened operator with omega = 0.11; shell pairs kept
   within 12 bohr; D_ij = u_ij exp(-0.5 r_ij).
-* ``config3_cluster``: 256 atoms at density 0.1 atoms/bohr^3 (cube edge
+* ``cluster_k4``: 256 atoms at density 0.1 atoms/bohr^3 (cube edge
   (N/0.1)^(1/3)), min separation 1.8, alternating heavy (s,s,p,p,d) and light
   (s,s,p) elements, 4 primitives per shell, exponents log-uniform in
   [0.1, 10]; bare Coulomb; FP32 cutoff 1e-6 on the product of Schwarz
-  factors; D as in config 1.
-* ``config4_batch``: 512 clusters with N uniform in {4..40}, each built with
-  the config-3 recipe and its own seed.
-* ``config5_requests``: a Poisson stream (rate 200/s) of requests, half
-  clusters (N log-uniform in [10, 500], config-3 recipe) and half periodic
-  diamond cells of 8..128 atoms (config-2 recipe), each of 10 SCF
+  factors; D as in the molecule.
+* ``cluster_batch``: 512 clusters with N uniform in {4..40}, each built with
+  the cluster recipe and its own seed.
+* ``request_stream``: a Poisson stream (rate 200/s) of requests, half
+  clusters (N log-uniform in [10, 500], cluster recipe) and half periodic
+  diamond cells of 8..128 atoms (cell recipe), each of 10 SCF
   iterations.
 
 Draw order for a system with seed s: ``rng = Generator(PCG64(s))``; atom
@@ -199,7 +199,7 @@ def random_cluster(n_atoms: int, seed: int, *, edge: Optional[float] = None,
                    heavy=(0, 0, 1, 1, 2), light=(0, 0, 1), nprim: int = 4,
                    exp_range=(0.1, 10.0), alternate: bool = True,
                    name: Optional[str] = None, **kw) -> System:
-    """Random molecular cluster (config-3 recipe by default)."""
+    """Random molecular cluster (the cluster recipe by default)."""
     rng = np.random.Generator(np.random.PCG64(seed))
     if edge is None:
         edge = (n_atoms / density) ** (1.0 / 3.0)
@@ -214,38 +214,38 @@ def random_cluster(n_atoms: int, seed: int, *, edge: Optional[float] = None,
     return _assemble(name or f"cluster{n_atoms}", seed, xyz, elem_of_atom, elements, **kw)
 
 
-def config1_molecule(seed: int = 1000) -> System:
+def molecule8(seed: int = 1000) -> System:
     """8-atom s,s,p molecule in a 10-bohr cube, bare Coulomb, FP64."""
     rng = np.random.Generator(np.random.PCG64(seed))
     xyz = _rejection_positions(rng, 8, 10.0, 2.0)
     elements = [_draw_element(rng, (0, 0, 1), 3, 0.1, 10.0)]
-    return _assemble("config1_molecule8_ssp_K3", seed, xyz, [0] * 8, elements,
+    return _assemble("molecule8_ssp_K3", seed, xyz, [0] * 8, elements,
                      op="coulomb", tau=1e-10, d_decay=0.3)
 
 
-def config2_diamond(seed: int = 1001, n=(2, 2, 2), a: float = 10.26, nprim: int = 6,
-                    exp_range=(0.05, 20.0), shells=(0, 0, 1, 1, 2), r_cut: float = 12.0,
-                    omega: float = 0.11, precision: str = "fp64", name: Optional[str] = None,
-                    **kw) -> System:
+def diamond_cell(seed: int = 1001, n=(2, 2, 2), a: float = 10.26, nprim: int = 6,
+                 exp_range=(0.05, 20.0), shells=(0, 0, 1, 1, 2), r_cut: float = 12.0,
+                 omega: float = 0.11, precision: str = "fp64", name: Optional[str] = None,
+                 **kw) -> System:
     """Periodic diamond cell, erfc operator, shell pairs within ``r_cut``."""
     rng = np.random.Generator(np.random.PCG64(seed))
     xyz, lat = diamond_supercell(a, *n)
     elements = [_draw_element(rng, shells, nprim, *exp_range)]
     kw.setdefault("tau", 1e-10)
     kw.setdefault("d_decay", 0.5)
-    nm = name or f"config2_diamond{xyz.shape[0]}_ssppd_K{nprim}_erfc"
+    nm = name or f"diamond{xyz.shape[0]}_ssppd_K{nprim}_erfc"
     return _assemble(nm, seed, xyz, [0] * xyz.shape[0], elements, lattice=lat,
                      pair_cutoff=r_cut, op="erfc", omega=omega, precision=precision,
                      fp32_cutoff=1e-6 if precision == "mixed" else 0.0, **kw)
 
 
-def config3_cluster(seed: int = 1002, n_atoms: int = 256, precision: str = "mixed") -> System:
-    return random_cluster(n_atoms, seed, name=f"config3_cluster{n_atoms}_K4",
+def cluster_k4(seed: int = 1002, n_atoms: int = 256, precision: str = "mixed") -> System:
+    return random_cluster(n_atoms, seed, name=f"cluster{n_atoms}_K4",
                           op="coulomb", tau=1e-10, precision=precision,
                           fp32_cutoff=1e-6 if precision == "mixed" else 0.0)
 
 
-def config4_batch(seed: int = 1003, n_clusters: int = 512, n_range=(4, 40),
+def cluster_batch(seed: int = 1003, n_clusters: int = 512, n_range=(4, 40),
                   precision: str = "mixed") -> List[System]:
     """Independent clusters for the fused batched launch."""
     rng = np.random.Generator(np.random.PCG64(seed))
@@ -264,10 +264,10 @@ class Request:
     n_iter: int = 10
 
 
-def config5_requests(seed: int = 1004, n_requests: int = 200, rate_per_s: float = 200.0,
-                     cluster_range=(10, 500), cell_atoms=(8, 16, 32, 64, 128),
-                     n_iter: int = 10, precision: str = "mixed",
-                     cluster_nprim: int = 4, cell_nprim: int = 6) -> List[Request]:
+def request_stream(seed: int = 1004, n_requests: int = 200, rate_per_s: float = 200.0,
+                   cluster_range=(10, 500), cell_atoms=(8, 16, 32, 64, 128),
+                   n_iter: int = 10, precision: str = "mixed",
+                   cluster_nprim: int = 4, cell_nprim: int = 6) -> List[Request]:
     """The first n_requests of the seeded Poisson request stream (50%
     clusters, 50% cells).  Draw order, request by request: the gap to the
     previous arrival, the kind, the cluster size, the cell size; so the
@@ -292,7 +292,7 @@ def config5_requests(seed: int = 1004, n_requests: int = 200, rate_per_s: float 
                                   fp32_cutoff=1e-6 if precision == "mixed" else 0.0)
         else:
             na = cell_atoms[int(cells[i])]
-            sysm = config2_diamond(seed=s, n=shapes[na], nprim=cell_nprim, precision=precision,
+            sysm = diamond_cell(seed=s, n=shapes[na], nprim=cell_nprim, precision=precision,
                                    name=f"req{i}_diamond{na}")
         out.append(Request(rid=i, arrival_s=float(t[i]), system=sysm, n_iter=n_iter))
     return out

@@ -6,10 +6,10 @@ build's error against the FP64 oracle reported per K block.
 Not collected by pytest (minutes of GPU time, tens of minutes of host time
 for the oracle's blocks, whose rows keep nearly every candidate quartet on
 this diffuse basis).  Run as
-``python tests/fullsize_config3.py --gpu-out P --forms fp64`` and
+``python tests/fullsize_cluster256.py --gpu-out P --forms fp64`` and
 ``... --gpu-out P --forms mixed`` on the GPU (counts, the timed build with a
 progress line per list chunk, K saved to P_fp64.npz / P_mixed.npz and a
-JSON line), then ``python tests/fullsize_config3.py --check P`` on any host
+JSON line), then ``python tests/fullsize_cluster256.py --check P`` on any host
 (mixed against FP64 on every element when both were saved, the oracle on
 the seeded blocks, per-block errors of each saved form, a JSON line);
 without --gpu-out or --check everything runs in one process.
@@ -54,7 +54,7 @@ def main():
         print(f"# {msg}", file=sys.stderr, flush=True)
 
     import systems
-    smx = systems.config3_cluster(n_atoms=args.atoms)
+    smx = systems.cluster_k4(n_atoms=args.atoms)
     s64 = smx.with_(precision="fp64")
     if args.check:
         return check(args, s64, log)
@@ -98,8 +98,8 @@ def main():
         print(json.dumps(out), flush=True)
         return 0
     for name, k in K.items():
-        np.savez(f"/tmp/_config3_{name}.npz", k=k, summary=json.dumps(out))
-    args.check = "/tmp/_config3"
+        np.savez(f"/tmp/_cluster256_{name}.npz", k=k, summary=json.dumps(out))
+    args.check = "/tmp/_cluster256"
     return check(args, s64, log)
 
 

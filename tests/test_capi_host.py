@@ -39,8 +39,8 @@ def _status_of(system):
     return hfx.lib().hfx_footprint(ctypes.byref(a.c), ctypes.byref(dev), ctypes.byref(per)), dev.value
 
 
-def test_footprint_of_config1():
-    st, dev = _status_of(systems.config1_molecule())
+def test_footprint_of_the_molecule():
+    st, dev = _status_of(systems.molecule8())
     assert st == hfx.HFX_OK and dev > 0
 
 
@@ -64,13 +64,13 @@ def test_footprint_of_config1():
      hfx.HFX_ERR_INVALID),
 ])
 def test_invalid_systems_rejected(mutate, expected):
-    st, _ = _status_of(mutate(systems.config1_molecule()))
+    st, _ = _status_of(mutate(systems.molecule8()))
     assert st == expected
     assert hfx.hfx_last_error()
 
 
 def test_plan_rejects_before_device_work():
-    s = systems.config1_molecule().with_(tau=-5.0)
+    s = systems.molecule8().with_(tau=-5.0)
     a = hfx._SystemArgs(s)
     h = ctypes.c_void_p(None)
     st = hfx.lib().hfx_plan(ctypes.byref(a.c), None, ctypes.byref(h))
@@ -87,13 +87,13 @@ def test_null_and_bogus_handles():
 def test_translation_range_checked_at_plan_time():
     # a cutoff long against the cell could need ket translations beyond the
     # 5-bit quartet encoding: refused when planning, never dropped silently
-    s = systems.config2_diamond(n=(1, 1, 1), nprim=1, shells=(0,), r_cut=50.0)
+    s = systems.diamond_cell(n=(1, 1, 1), nprim=1, shells=(0,), r_cut=50.0)
     with pytest.raises(hfx.HfxError) as e:
         hfx.hfx_footprint(s)
     assert e.value.status == hfx.HFX_ERR_UNSUPPORTED
     assert "translations" in str(e.value)
     # the benchmark cell is far inside the range
-    dev, per = hfx.hfx_footprint(systems.config2_diamond())
+    dev, per = hfx.hfx_footprint(systems.diamond_cell())
     assert dev > 0 and per == 8
 
 

@@ -18,7 +18,7 @@ def _blocks(s, n=40, seed=3):
 
 
 def test_series_equals_each_iteration():
-    s = systems.config2_diamond(n=(1, 1, 1), name="cell8")
+    s = systems.diamond_cell(n=(1, 1, 1), name="cell8")
     b = _blocks(s)
     ser = systems.density_series(s, b, 5)
     assert len(ser) == 5
@@ -33,7 +33,7 @@ def test_series_equals_each_iteration():
 
 
 def test_series_follows_its_definition():
-    s = systems.config2_diamond(n=(1, 1, 1), name="cell8")
+    s = systems.diamond_cell(n=(1, 1, 1), name="cell8")
     b = _blocks(s, n=12, seed=5)
     noise = 1e-3
     d0 = systems.density_series(s, b, 1)[0]

@@ -27,16 +27,16 @@ def _density(system, blocks, iteration=0):
 
 def _tiny_cell(**kw):
     kw.setdefault("seed", 77)
-    return systems.config2_diamond(n=(1, 1, 1), nprim=2, shells=(0, 1, 2), r_cut=4.6, **kw)
+    return systems.diamond_cell(n=(1, 1, 1), nprim=2, shells=(0, 1, 2), r_cut=4.6, **kw)
 
 
 def _systems():
     return [
-        systems.config1_molecule(),
+        systems.molecule8(),
         _tiny_cell(seed=301),
         systems.random_cluster(5, 2025, nprim=2, op="coulomb"),
         _tiny_cell(seed=302).with_(precision="mixed", fp32_cutoff=1e-4),
-        systems.config1_molecule(seed=1003).with_(op="erfc", omega=0.2),
+        systems.molecule8(seed=1003).with_(op="erfc", omega=0.2),
     ]
 
 
@@ -84,7 +84,7 @@ def test_multi_repeat_and_subset_cache():
 
 
 def test_multi_rejects_duplicates_and_destroyed():
-    s = systems.config1_molecule()
+    s = systems.molecule8()
     p = hfx.Plan(s)
     D = torch.zeros(p.nnz, dtype=torch.float64, device=DEV)
     with pytest.raises(hfx.HfxError):

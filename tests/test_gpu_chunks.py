@@ -26,7 +26,7 @@ def _density(system, blocks):
 
 def _tiny_cell(**kw):
     kw.setdefault("seed", 77)
-    return systems.config2_diamond(n=(1, 1, 1), nprim=2, shells=(0, 1, 2), r_cut=4.6, **kw)
+    return systems.diamond_cell(n=(1, 1, 1), nprim=2, shells=(0, 1, 2), r_cut=4.6, **kw)
 
 
 def _oracle_K(system, D):
@@ -53,10 +53,10 @@ def _run(system, limit, flags=hfx.HFX_SYNC):
     return plan, D, Dd, K0.cpu().numpy(), K1.cpu().numpy(), i0, i1
 
 
-@pytest.mark.parametrize("which", ["config1", "cell", "cell_mixed", "cluster_mixed"])
+@pytest.mark.parametrize("which", ["molecule8", "cell", "cell_mixed", "cluster_mixed"])
 def test_chunked_equals_whole_and_oracle(which, oracle_cache):
-    if which == "config1":
-        s = systems.config1_molecule()
+    if which == "molecule8":
+        s = systems.molecule8()
     elif which == "cell":
         s = _tiny_cell()
     elif which == "cell_mixed":
@@ -83,7 +83,7 @@ def test_chunked_equals_whole_and_oracle(which, oracle_cache):
 
 
 def test_chunk_limit_below_one_work_item_is_an_error():
-    s = systems.config1_molecule()
+    s = systems.molecule8()
     plan = hfx.Plan(s)
     D = _density(s, plan.blocks)
     Dd = torch.from_numpy(D).to(DEV)
@@ -121,7 +121,7 @@ def test_chunked_build_keeps_no_list_and_graph_builds_run_eagerly():
 
 
 def test_fused_multi_plan_build_in_chunks():
-    ss = [systems.config1_molecule(), systems.random_cluster(5, seed=41, nprim=2)]
+    ss = [systems.molecule8(), systems.random_cluster(5, seed=41, nprim=2)]
     plans = [hfx.Plan(s) for s in ss]
     Ds = [torch.from_numpy(_density(s, p.blocks)).to(DEV) for s, p in zip(ss, plans)]
     Kw = [torch.zeros_like(d) for d in Ds]

@@ -23,13 +23,13 @@ def _K(system, blocks):
 @pytest.mark.parametrize("which", ["cell", "cell_cartesian_d", "diamond64", "molecule"])
 def test_kspace_against_oracle(which):
     if which == "molecule":
-        s = systems.config1_molecule()
+        s = systems.molecule8()
         kp = np.zeros((1, 3))
     else:
         if which == "diamond64":
-            s = systems.config2_diamond()
+            s = systems.diamond_cell()
         else:
-            s = systems.config2_diamond(n=(1, 1, 1), nprim=2, shells=(0, 1, 2), r_cut=4.6, seed=79,
+            s = systems.diamond_cell(n=(1, 1, 1), nprim=2, shells=(0, 1, 2), r_cut=4.6, seed=79,
                                         spherical_d=(which == "cell"))
         rec = 2 * np.pi * np.linalg.inv(np.asarray(s.lattice)).T
         rng = np.random.default_rng(3)
@@ -50,7 +50,7 @@ def test_kspace_against_oracle(which):
 
 
 def test_kspace_rejects_bad_arguments():
-    s = systems.config1_molecule()
+    s = systems.molecule8()
     plan = hfx.Plan(s)
     K = torch.zeros(plan.nnz, dtype=torch.float64, device=DEV)
     H = torch.zeros((1, 40, 40, 2), dtype=torch.float64, device=DEV)

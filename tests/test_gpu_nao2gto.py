@@ -44,7 +44,7 @@ def test_fitted_basis_build_against_oracle(which):
     if which == "cluster":
         s = _system(systems.random_cluster(4, seed=91, nprim=1), 3)
     else:
-        s = _system(systems.config2_diamond(n=(1, 1, 1), nprim=1, shells=(0,), r_cut=4.6, seed=92), 2)
+        s = _system(systems.diamond_cell(n=(1, 1, 1), nprim=1, shells=(0,), r_cut=4.6, seed=92), 2)
     plan = hfx.Plan(s)
     vals = systems.density_blocks(s, plan.blocks.astype(np.int64))
     D = np.concatenate([v.ravel() for v in vals])

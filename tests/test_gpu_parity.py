@@ -41,12 +41,12 @@ class Case:
 
 def _tiny_cell(**kw):
     kw.setdefault("seed", 77)
-    return systems.config2_diamond(n=(1, 1, 1), nprim=2, shells=(0, 1, 2), r_cut=4.6, **kw)
+    return systems.diamond_cell(n=(1, 1, 1), nprim=2, shells=(0, 1, 2), r_cut=4.6, **kw)
 
 
 @pytest.fixture(scope="module")
 def c1():
-    return Case(systems.config1_molecule())
+    return Case(systems.molecule8())
 
 
 @pytest.fixture(scope="module")
@@ -76,10 +76,10 @@ def test_pmax_close_spd(cell):
     assert np.allclose(pm, cell.o.Pmax, rtol=1e-15, atol=0)
 
 
-def test_K_config1_full(c1):
+def test_K_molecule_full(c1):
     Kref, _ = c1.o.build_K()
     err = np.max(np.abs(c1.K - Kref))
-    print(f"config1: {c1.info['n_quartets']} quartets, max|dK| = {err:.3e}")
+    print(f"molecule: {c1.info['n_quartets']} quartets, max|dK| = {err:.3e}")
     assert err <= TOL_FP64
 
 
@@ -158,7 +158,7 @@ def test_repeat_builds_agree(c1):
 
 
 def test_zero_density_gives_zero():
-    s = systems.config1_molecule(seed=1234)
+    s = systems.molecule8(seed=1234)
     plan = hfx.Plan(s)
     D = torch.zeros(plan.nnz, dtype=torch.float64, device=DEV)
     K = torch.full_like(D, 7.0)
@@ -168,7 +168,7 @@ def test_zero_density_gives_zero():
 
 
 def test_huge_tau_screens_everything():
-    s = systems.config1_molecule().with_(tau=1e30)
+    s = systems.molecule8().with_(tau=1e30)
     plan = hfx.Plan(s)
     D = torch.from_numpy(_density(s, plan.blocks)).to(DEV)
     K = torch.full_like(D, 3.0)
@@ -189,7 +189,7 @@ def test_single_shell_atom():
 
 
 def test_destroyed_plan_is_rejected():
-    s = systems.config1_molecule()
+    s = systems.molecule8()
     plan = hfx.Plan(s)
     h = plan.handle.value
     plan.destroy()
@@ -244,7 +244,7 @@ def test_mixed_precision_periodic_erfc(cutoff):
 
 
 @pytest.mark.parametrize("cutoff", [1e-6, 1e-3])
-def test_mixed_precision_cluster_config3_recipe(cutoff):
+def test_mixed_precision_cluster_recipe(cutoff):
     # small enough for the oracle: 5 atoms (3 heavy, 2 light), 3 primitives.
     # At the recipe's 1e-6 this cluster's quartets below the cutoff all fall
     # in classes that stay FP64; 1e-3 puts d-shell classes on the FP32 list.
@@ -359,7 +359,7 @@ def test_full_size_list_on_sampled_bra_pairs():
     sample of shell pairs (three of each pair class), the orbits of the
     GPU's list containing the pair equal the oracle's kept orbits with that
     bra pair (the oracle screening with the GPU's Q and P_max: exact)."""
-    s = systems.config2_diamond()
+    s = systems.diamond_cell()
     plan = hfx.Plan(s)
     D = _density(s, plan.blocks)
     Dd = torch.from_numpy(D).to(DEV)
@@ -407,7 +407,7 @@ def test_full_size_sampled_parity(precision, cutoff):
     the benchmark's cutoff 1e-4 and at 1e-6 (1e-7), the quartets below the
     cutoff taking the FP32 kernels."""
     from tests.helpers import canonical_keys, gpu_rows, oracle_quartet_instances, orbit_members, to_gpu_quartets
-    s = systems.config2_diamond(precision=precision)
+    s = systems.diamond_cell(precision=precision)
     if precision == "mixed":
         s = s.with_(fp32_cutoff=cutoff)
     plan = hfx.Plan(s)
@@ -467,8 +467,8 @@ def test_supercell_tiles_the_cell(rep):
     density tiled, gives the cell's K tiled (same pattern, same Q and P_max
     per corresponding block, so the same screened terms)."""
     kw = dict(seed=79, nprim=2, shells=(0, 1, 2), r_cut=4.6)
-    small = systems.config2_diamond(n=(1, 1, 1), **kw)
-    big = systems.config2_diamond(n=rep, **kw)
+    small = systems.diamond_cell(n=(1, 1, 1), **kw)
+    big = systems.diamond_cell(n=rep, **kw)
     assert np.array_equal(small.prim_exp, big.prim_exp[: len(small.prim_exp)])
     ps, pb = hfx.Plan(small), hfx.Plan(big)
     nsh = 3                                      # shells per atom

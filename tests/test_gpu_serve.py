@@ -17,7 +17,7 @@ pytestmark = pytest.mark.gpu
 
 
 def _tiny_cell(seed, **kw):
-    return systems.config2_diamond(seed=seed, n=(1, 1, 1), nprim=2, shells=(0, 1, 2), r_cut=4.6, **kw)
+    return systems.diamond_cell(seed=seed, n=(1, 1, 1), nprim=2, shells=(0, 1, 2), r_cut=4.6, **kw)
 
 
 def _requests():
@@ -25,10 +25,10 @@ def _requests():
         # a build here takes milliseconds: the first request runs 8
         # iterations, the others arrive within its first one or two
         ServeRequest(0, _tiny_cell(501), n_iter=8, arrival_s=0.0),
-        ServeRequest(1, systems.config1_molecule(seed=502), n_iter=3, arrival_s=0.0005),
+        ServeRequest(1, systems.molecule8(seed=502), n_iter=3, arrival_s=0.0005),
         ServeRequest(2, _tiny_cell(503).with_(precision="mixed", fp32_cutoff=1e-6), n_iter=3, arrival_s=0.001),
         ServeRequest(3, systems.random_cluster(5, 504, nprim=2, op="coulomb"), n_iter=2, arrival_s=0.0015),
-        ServeRequest(4, systems.config1_molecule(seed=505).with_(op="erfc", omega=0.2), n_iter=2, arrival_s=0.002),
+        ServeRequest(4, systems.molecule8(seed=505).with_(op="erfc", omega=0.2), n_iter=2, arrival_s=0.002),
     ]
 
 

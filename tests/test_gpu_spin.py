@@ -24,13 +24,13 @@ def _dens(system, blocks, seed_shift=0):
 
 def _tiny_cell(**kw):
     kw.setdefault("seed", 77)
-    return systems.config2_diamond(n=(1, 1, 1), nprim=2, shells=(0, 1, 2), r_cut=4.6, **kw)
+    return systems.diamond_cell(n=(1, 1, 1), nprim=2, shells=(0, 1, 2), r_cut=4.6, **kw)
 
 
-@pytest.mark.parametrize("which", ["config1", "cell", "cell_mixed", "cell_chunked"])
+@pytest.mark.parametrize("which", ["molecule8", "cell", "cell_mixed", "cell_chunked"])
 def test_spin_build_against_oracle(which):
-    if which == "config1":
-        s = systems.config1_molecule()
+    if which == "molecule8":
+        s = systems.molecule8()
     elif which == "cell_mixed":
         s = _tiny_cell(precision="mixed").with_(fp32_cutoff=1e-2)
     else:

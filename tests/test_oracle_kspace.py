@@ -14,7 +14,7 @@ ALPHA = 0.25  # HSE06
 
 
 def _cell(seed=79):
-    return systems.config2_diamond(n=(1, 1, 1), nprim=2, shells=(0, 1, 2), r_cut=4.6, seed=seed)
+    return systems.diamond_cell(n=(1, 1, 1), nprim=2, shells=(0, 1, 2), r_cut=4.6, seed=seed)
 
 
 def _pattern(s):
@@ -81,7 +81,7 @@ def test_reciprocal_lattice_relation():
 
 def test_band_folding_of_a_supercell():
     s = _cell()
-    sup = systems.config2_diamond(n=(2, 1, 1), nprim=2, shells=(0, 1, 2), r_cut=4.6, seed=79)
+    sup = systems.diamond_cell(n=(2, 1, 1), nprim=2, shells=(0, 1, 2), r_cut=4.6, seed=79)
     bs, os_ = _pattern(s)
     bb, ob = _pattern(sup)
     Ks = _sym_K(s, bs)

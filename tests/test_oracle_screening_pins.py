@@ -148,7 +148,7 @@ def test_schwarz_factors_against_independent_integrals(periodic, op):
 
 def test_schwarz_contracted_ss_pairs_of_the_molecule_workload():
     # every s-s block of the 8-atom workload (3 primitives per shell)
-    s = systems.config1_molecule()
+    s = systems.molecule8()
     o = oracle.Oracle(s)
     Q = o.schwarz()
     ls = s.shell_l

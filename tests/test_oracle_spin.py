@@ -19,7 +19,7 @@ def _dens(system, blocks, seed_shift=0):
 
 @pytest.fixture(scope="module")
 def cell():
-    s = systems.config2_diamond(n=(1, 1, 1), nprim=2, shells=(0, 1, 2), r_cut=4.6, seed=77)
+    s = systems.diamond_cell(n=(1, 1, 1), nprim=2, shells=(0, 1, 2), r_cut=4.6, seed=77)
     o = oracle.Oracle(s)
     o.schwarz()
     return s, o
@@ -51,7 +51,7 @@ def test_zero_beta_and_swap(cell):
 
 
 def test_unscreened_spin_K_is_each_densitys_plain_sum():
-    s = systems.config1_molecule().with_(tau=0.0)
+    s = systems.molecule8().with_(tau=0.0)
     o = oracle.Oracle(s)
     o.schwarz()
     Da = _dens(s, o.blocks)

@@ -23,7 +23,7 @@ def _blk(o, K, i):
 
 @pytest.fixture(scope="module")
 def c1():
-    s = systems.config1_molecule()
+    s = systems.molecule8()
     o = oracle.Oracle(s)
     o.schwarz()
     D = o.density_from_system()
@@ -35,7 +35,7 @@ def c1():
 
 @pytest.fixture(scope="module")
 def tiny_cell():
-    s = systems.config2_diamond(seed=77, n=(1, 1, 1), nprim=2, shells=(0, 1, 2), r_cut=4.6)
+    s = systems.diamond_cell(seed=77, n=(1, 1, 1), nprim=2, shells=(0, 1, 2), r_cut=4.6)
     o = oracle.Oracle(s)
     o.schwarz()
     D = o.density_from_system()
@@ -171,8 +171,8 @@ def test_K_from_orbits_equals_plain_loop():
     kept orbit, reproduces the plain screened loop (pins K_from_quartets for
     the sampled full-size parity test)."""
     from tests.helpers import canonical_keys, oracle_quartet_instances, orbit_members
-    for s in (systems.config1_molecule(seed=321),
-              systems.config2_diamond(seed=322, n=(1, 1, 1), nprim=1, shells=(0, 1), r_cut=4.0)):
+    for s in (systems.molecule8(seed=321),
+              systems.diamond_cell(seed=322, n=(1, 1, 1), nprim=1, shells=(0, 1), r_cut=4.0)):
         o = oracle.Oracle(s)
         o.schwarz()
         o.set_density(o.density_from_system())

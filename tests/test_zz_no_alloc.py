@@ -49,11 +49,11 @@ def _case(system):
 
 def _tiny_cell(**kw):
     kw.setdefault("seed", 77)
-    return systems.config2_diamond(n=(1, 1, 1), nprim=2, shells=(0, 1, 2), r_cut=4.6, **kw)
+    return systems.diamond_cell(n=(1, 1, 1), nprim=2, shells=(0, 1, 2), r_cut=4.6, **kw)
 
 
 def test_noalloc_two_calls_second_smaller():
-    cases = [_case(_tiny_cell()), _case(systems.config1_molecule())]
+    cases = [_case(_tiny_cell()), _case(systems.molecule8())]
     # the larger system first, then the smaller one
     cases.sort(key=lambda c: -c[4]["n_quartets"])
     counts = []
@@ -91,7 +91,7 @@ def test_noalloc_in_chunks_and_mixed_precision():
 
 
 def test_noalloc_rejects_other_flags():
-    s = systems.config1_molecule()
+    s = systems.molecule8()
     plan, D, Dd, Kref, iref = _case(s)
     Kn = torch.zeros_like(Dd)
     for f in (hfx.HFX_TIMING, hfx.HFX_GRAPH):
