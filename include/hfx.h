@@ -123,13 +123,15 @@ typedef struct {
 /* Device bytes hfx_plan would allocate for this system (its tables and its
  * own one-plan batch), plus the plan's share of a fused multi-plan batch,
  * excluding the per-build quartet lists (8 bytes per screened quartet,
- * reported in *list_bytes_per_quartet) and the second-spin arrays of
- * hfx_build_K_spin.  Validates like hfx_plan; allocates nothing on the
- * device. */
+ * reported in *list_bytes_per_quartet), the second-spin arrays of
+ * hfx_build_K_spin and the library's per-device static arrays (the Boys
+ * table, 87 KB, shared by all plans, and the allocation-free build's
+ * scratch).  Validates like hfx_plan; allocates nothing on the device. */
 hfx_status hfx_footprint(const hfx_system *sys, size_t *device_bytes, size_t *list_bytes_per_quartet);
 
 /* Validate, normalise contractions, build the pattern, shell-pair and
- * primitive-pair tables and the block lookup, and upload them.  stream:
+ * primitive-pair tables and the block lookup, and upload them; the first
+ * plan on a device also fills that device's Boys table.  stream:
  * hipStream_t (NULL = default stream).  *out receives the plan. */
 hfx_status hfx_plan(const hfx_system *sys, void *stream, hfx_plan_t *out);
 
