@@ -102,3 +102,16 @@ def test_nao2gto_and_progress_symbols_are_host_callable():
     r, R = systems.nao_radial(2, 1.1, 6.0)
     e, c, rms = hfx.nao2gto_fit(2, r, R, 4)
     assert np.all(np.diff(e) > 0) and rms < 0.05
+
+
+def test_missing_library_raises_and_nothing_falls_back(monkeypatch):
+    # the binding loads only the built library; without it every call fails
+    # loudly (there is no CPU path to fall back to)
+    from paper_2009_03555_amd import hfx as H
+    monkeypatch.setattr(H, "_lib", None)
+    monkeypatch.setattr(H, "LIB_PATH", "/nonexistent/libhfx.so")
+    with pytest.raises(ImportError):
+        H.lib()
+    import systems
+    with pytest.raises(ImportError):
+        H.hfx_footprint(systems.molecule8())
